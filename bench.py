@@ -1,0 +1,246 @@
+"""Throughput of the fused D3Q7 stream-and-collide update on one MI355X.
+
+Workload: the supersonic Taylor-Green vortex at 512^3 (M0 = 1.25, Re = 1600,
+Pr = 0.71, mu ~ T^0.76), seeded synthetic initial field, populations stored
+FP32 (the headline number) and as FP16 / BF16 deviations (reported beside it).
+One step is one in-place pass of the whole update over all 134M cells.
+
+Prints one JSON line:
+  value      MLUPS of the FP32-storage update (whole job, inputs resident in HBM)
+  roofline   HBM roofline of the update kernel: algorithmic bytes per launch
+             (98 populations read + written per cell) / mean launch time from
+             HIP events on the launch stream, against 8 TB/s
+  cpu_baseline  the FP64 NumPy oracle on a bounded sample (64^3 Taylor-Green)
+             on this host's cores
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512]
+                       [--storage all|fp32|fp16|bf16] [--no-cpu] [--batch]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBPS = 8000.0
+METRIC = "MLUPS + HBM GB/s (% peak), FP32 vs FP16-storage, supersonic TGV 512^3"
+STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2}
+BYTES_PER_POP = {"fp32": 4, "fp16": 2, "bf16": 2}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_tgv512.json")
+KERNEL_SOURCES = ["paper_2608_13437_amd/csrc/update.hip", "paper_2608_13437_amd/csrc/cnsf_impl.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def load_lattice_tgv(cnsf, n, storage, slab=16):
+    import workloads as W
+    prm = W.tgv_params(n, storage=STORAGES[storage])
+    L = cnsf.Lattice(prm)
+    t0 = time.perf_counter()
+    for z0 in range(0, n, slab):
+        z1 = min(n, z0 + slab)
+        L.set_state(W.tgv_slab(prm, z0, z1), z0=z0)
+    log(f"  set_state {n}^3 {storage}: {time.perf_counter() - t0:.1f} s")
+    return L, prm
+
+
+def time_update(L, steps, warmup):
+    """Mean per-launch time (ms) from HIP events recorded on the launch stream."""
+    import torch
+    L.step(warmup)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record()
+    for s in range(steps):
+        L.step(1)
+        ev[s + 1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[s].elapsed_time(ev[s + 1]) for s in range(steps)]
+    return float(np.mean(per)), float(np.min(per)), wall
+
+
+def copy_bandwidth(cnsf, nbytes=8 << 30, reps=10):
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    s = torch.cuda.current_stream().cuda_stream
+    cnsf.cnsf_hbm_copy(dst.data_ptr(), src.data_ptr(), nbytes, s)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        cnsf.cnsf_hbm_copy(dst.data_ptr(), src.data_ptr(), nbytes, s)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(n=64, steps=12):
+    """The FP64 oracle (NumPy, single-threaded elementwise code) on a bounded sample."""
+    import warnings
+    warnings.simplefilter("ignore", RuntimeWarning)
+    import workloads as W
+    from oracle import lbm
+    case = W.tgv(n)
+    f = lbm.init_populations(case.Q0, case.params)
+    f = lbm.step(f, case.params)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f = lbm.step(f, case.params)
+    dt = time.perf_counter() - t0
+    return dict(value=round(n ** 3 * steps / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
+                sample=f"Taylor-Green {n}^3, {steps} steps of the FP64 NumPy oracle ({dt:.1f} s)")
+
+
+def traffic_entry(storage, mean_ms):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if current."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    rec = t.get(storage)
+    if not rec or t.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_batch(cnsf, steps, warmup):
+    """Ensemble of 64 uneven Taylor-Green lattices (FP16 storage): graph replay vs per-member launches."""
+    import torch
+    import workloads as W
+    cases = W.batch_ensemble(materialize=False)
+    B = cnsf.Batch([c.params for c in cases])
+    for j, c in enumerate(cases):
+        B.set_state(j, W.tgv_slab(c.params, 0, c.params["nz"]))
+    B.autotune(os.path.join(ROOT, "profiles", "batch_autotune.json"), steps_per_trial=10)
+    out = {}
+    for name, mode in (("graph", 1), ("launch", 0), ("sequential", 2)):
+        B.step(warmup, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.step(steps, mode)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = round(B.ncells * steps / dt / 1e6, 1)
+    out["cells"] = B.ncells
+    out["members"] = len(cases)
+    B.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=6)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--storage", default="all")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="GIB",
+                    help="only run the plain copy kernel on GIB GiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU halo-exchange path is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2608_13437_amd as cnsf
+    cnsf.library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_only:
+        gbps = copy_bandwidth(cnsf, nbytes=args.copy_only << 30, reps=args.steps)
+        print(json.dumps({"copy_bytes_per_launch": 2 * (args.copy_only << 30), "copy_GBps": round(gbps, 1),
+                          "launches": args.steps + 1}), flush=True)
+        return
+
+    storages = list(STORAGES) if args.storage == "all" else [args.storage]
+    n = args.n
+    cells = n ** 3
+    res = {}
+    for st in storages:
+        L, prm = load_lattice_tgv(cnsf, n, st)
+        L.set_launch(256, True)
+        mean_ms, min_ms, wall = time_update(L, args.steps, args.warmup)
+        d = L.diagnostics(spectral=False)
+        alg_bytes = 98 * 2 * BYTES_PER_POP[st] * cells
+        res[st] = dict(ms=mean_ms, min_ms=min_ms, wall=wall, mlups=cells / (mean_ms * 1e-3) / 1e6,
+                       gbps=alg_bytes / (mean_ms * 1e-3) / 1e9, bytes=alg_bytes, finite=d["nonfinite"] == 0)
+        log(f"  {st}: {mean_ms:.3f} ms/step, {res[st]['mlups']:.0f} MLUPS, {res[st]['gbps']:.0f} GB/s")
+        L.close()
+        del L
+        torch.cuda.empty_cache()
+
+    head = "fp32" if "fp32" in res else storages[0]
+    r = res[head]
+    copy_gbps = None if args.no_copy else round(copy_bandwidth(cnsf), 1)
+    traffic = traffic_entry(head, r["ms"])
+    out = {
+        "metric": METRIC,
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"supersonic Taylor-Green vortex {n}^3 (M0 1.25, Re 1600), D3Q7 14-component "
+                        f"stream-collide, {head} populations, AA in-place",
+            "cells": cells, "storage": head, "block": 256, "xcd_remap": True,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(r["gbps"], 1),
+            "peak": PEAK_HBM_GBPS,
+            "unit": "GB/s",
+            "frac": round(r["gbps"] / PEAK_HBM_GBPS, 4),
+            "traffic": traffic,
+        },
+        "hbm_copy_GBps": copy_gbps,
+        "variants": {st: {"ms_per_step": round(v["ms"], 4), "MLUPS": round(v["mlups"], 1),
+                          "GBps": round(v["gbps"], 1), "frac_peak": round(v["gbps"] / PEAK_HBM_GBPS, 4),
+                          "speedup_vs_fp32": (round(res["fp32"]["ms"] / v["ms"], 3) if "fp32" in res else None),
+                          "finite": v["finite"]}
+                     for st, v in res.items()},
+        "kernel_hash": kernel_hash(),
+    }
+    if args.batch:
+        out["batch"] = run_batch(cnsf, 20, 4)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

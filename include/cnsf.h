@@ -1,0 +1,219 @@
+/*
+ * cnsf.h - C ABI of the D3Q7 compressible Navier-Stokes-Fourier lattice
+ * Boltzmann hot path for MI355X (gfx950).
+ *
+ * The method: the fourteen-component state Q = (rho, rho u, E, tau, q) of
+ * Eq. (2) (Section 2.1), one set of seven D3Q7 populations per component with
+ * a linear equilibrium embedding the flux in its first moment, zeroth-moment
+ * recovery and BGK collide-and-stream with the source on the lattice weights
+ * (Section 2.2), the relaxation rate lowered per cell by the local one-sided
+ * shock sensor of Eqs. (3)-(6) (Section 2.3), and the volume averages of
+ * Eq. (7) (Section 3.2).
+ *
+ * Conventions for every call:
+ *  - Component order k: 0 rho, 1-3 rho*u_{x,y,z}, 4 E, 5-10 tau_{xx,yy,zz,xy,xz,yz},
+ *    11-13 q_{x,y,z}.  tau is the Newtonian-sign stress of Eq. (2).
+ *  - Field arrays are FP64, component-major, x fastest: Q[k][z][y][x].
+ *  - Pointers marked "host or device" are read or written according to the
+ *    `where` argument (CNSF_HOST or CNSF_DEVICE); device pointers must be on
+ *    the device that was current at cnsf_create.
+ *  - Every call returns CNSF_OK or an error code; cnsf_last_error() gives the
+ *    message of the last failing call on the calling thread.  No C++
+ *    exception crosses this interface.
+ *  - Work is enqueued on the HIP stream given at creation.  Calls that return
+ *    data to the host synchronise that stream.
+ */
+#ifndef CNSF_H
+#define CNSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CNSF_NCOMP 14
+#define CNSF_NVEL 7
+#define CNSF_NPOP 98
+#define CNSF_ABI_VERSION 1
+
+enum cnsf_status {
+  CNSF_OK = 0,
+  CNSF_E_INVALID = 1, /* a parameter or argument is out of range */
+  CNSF_E_NOMEM = 2,   /* a buffer is too small or an allocation failed */
+  CNSF_E_DEVICE = 3,  /* a HIP call failed */
+  CNSF_E_STATE = 4,   /* a field holds rho <= 0, p <= 0 or a non-finite value */
+  CNSF_E_SIZE = 5     /* mismatched sizes (checkpoint, slab range) */
+};
+
+enum cnsf_visc_law { CNSF_VISC_CONST = 0, CNSF_VISC_SUTHERLAND = 1, CNSF_VISC_POWER = 2 };
+enum cnsf_bc { CNSF_BC_PERIODIC = 0, CNSF_BC_WALL = 1, CNSF_BC_DIRICHLET = 2 };
+enum cnsf_storage { CNSF_STORAGE_FP32 = 0, CNSF_STORAGE_FP16 = 1, CNSF_STORAGE_BF16 = 2 };
+enum cnsf_where { CNSF_HOST = 0, CNSF_DEVICE = 1 };
+
+/*
+ * Parameters of one lattice (Table "Parameters" of Section 2.3 and the
+ * declaration listing of Section 2.1).  Physical units throughout.
+ *  size            sizeof(cnsf_params); set by cnsf_params_default.
+ *  nx, ny, nz      lattice cells (>= 1 each; nx*ny*nz < 2^31).
+ *  dx, dt          cell size and time step (> 0); lambda = dx/dt.
+ *  gamma           adiabatic index (> 1).
+ *  mu0, T_ref      reference viscosity (>= 0) and temperature (> 0).
+ *  visc_law        mu_T(T): CONST mu0; SUTHERLAND mu0 (1+S) th^1.5/(th+S) with
+ *                  S = visc_param and th = T/T_ref; POWER mu0 th^visc_param.
+ *  prandtl         kappa = gamma mu0 / ((gamma-1) Pr) (> 0).
+ *  tau_R, tau_q    relaxation times of tau and q (> 0).
+ *  f_mu            background dissipation of Eq. (6): tau_base = 1/2 +
+ *                  4 f_mu (mu_T/rho) dt/dx^2, evaluated per cell (>= 0).
+ *  tau_base_override  if > 0, a constant tau_base (in time steps) instead.
+ *  C_sigma, J_min, omega_min  sensor slope, threshold and rate floor of
+ *                  Eqs. (3)-(5); C_sigma = 0 disables the sensor.
+ *  bc_x            x-ends: PERIODIC; WALL (halfway bounce-back with the mirror
+ *                  sign of each component); DIRICHLET (incoming populations set
+ *                  to the equilibrium of Q_left / Q_right).  y and z periodic.
+ *  Q_left, Q_right uniform 14-vectors for DIRICHLET.
+ *  storage         population storage: FP32, or FP16 / BF16 deviations.
+ *  Q_ref           reference state of the shifted storage: populations are
+ *                  stored as g = (f - f^eq(Q_ref)) / s_k.
+ *  storage_scale   s_k per component (power of two recommended); 0 means 1.
+ *  a_ref           optional largest characteristic speed; if > 0, creation
+ *                  rejects a_ref dt/dx > 1/2 (sub-characteristic bound).
+ */
+typedef struct cnsf_params {
+  uint32_t size;
+  int32_t nx, ny, nz;
+  double dx, dt;
+  double gamma, mu0, T_ref;
+  int32_t visc_law;
+  double visc_param;
+  double prandtl;
+  double tau_R, tau_q;
+  double f_mu, tau_base_override;
+  double C_sigma, J_min, omega_min;
+  int32_t bc_x;
+  double Q_left[CNSF_NCOMP];
+  double Q_right[CNSF_NCOMP];
+  int32_t storage;
+  double Q_ref[CNSF_NCOMP];
+  double storage_scale[CNSF_NCOMP];
+  double a_ref;
+} cnsf_params;
+
+/* Volume diagnostics (FP64 reductions on the device).  E_k, eps_s, eps_d follow
+ * Eq. (7) with rho_ref = 1 and mu_local from the lattice's viscosity law;
+ * eps_s / eps_d use spectral derivatives along each periodic axis (zero when
+ * not requested or when bc_x is not periodic). */
+typedef struct cnsf_diag {
+  int64_t step;
+  double time;
+  double mass, momentum[3], energy; /* sums over cells of rho, rho u, E */
+  double E_k;                       /* <rho |u|^2 / 2> */
+  double eps_s, eps_d;              /* <mu |curl u|^2>, 4/3 <mu (div u)^2> */
+  double min_rho, min_p;
+  double sensor_fraction;           /* fraction of cells with chi > 0 */
+  int64_t nonfinite;                /* cells with a non-finite moment */
+} cnsf_diag;
+
+enum cnsf_diag_flags { CNSF_DIAG_SUMS = 0, CNSF_DIAG_SPECTRAL = 1 };
+
+typedef struct cnsf_lattice cnsf_lattice;
+
+/* Fill *p with defaults: gamma 1.4, constant viscosity 0, Pr 0.71, sensor
+ * off, periodic, FP32 storage, zero reference state.  Never fails for p != NULL. */
+int cnsf_params_default(cnsf_params* p);
+
+/* Device bytes of the population array for p: 98 planes of the padded cell
+ * count, 4 bytes (FP32) or 2 bytes (FP16 / BF16) per population.  The array is
+ * the only large allocation; the in-place (AA) streaming needs no second copy. */
+int cnsf_required_bytes(const cnsf_params* p, size_t* bytes);
+
+/* Validate p, derive the lattice constants and bind the population array.
+ *  dev_buf  caller-owned device buffer of at least cnsf_required_bytes bytes,
+ *           256-byte aligned; never freed by the library.  NULL: the library
+ *           allocates (hipMalloc) and frees it in cnsf_destroy.
+ *  stream   hipStream_t on which all work is enqueued (NULL: default stream).
+ * Errors: CNSF_E_INVALID (any range listed under cnsf_params, omega outside
+ * (0,2), unknown enum, sub-characteristic bound), CNSF_E_NOMEM, CNSF_E_DEVICE. */
+int cnsf_create(const cnsf_params* p, void* dev_buf, size_t bytes, void* stream, cnsf_lattice** out);
+
+/* Release library-owned device memory and the handle. */
+int cnsf_destroy(cnsf_lattice* lat);
+
+/* Set the populations of z-planes [z0, z0+nzs) to f^eq(Q) (Section 2.2
+ * initial state).  Q (host or device) is [14][nzs][ny][nx].  Resets the
+ * step counter and parity when z0 == 0.  CNSF_E_STATE if a cell has rho <= 0,
+ * p <= 0 or a non-finite value (checked on the device). */
+int cnsf_set_state(cnsf_lattice* lat, const double* Q, int32_t z0, int32_t nzs, int32_t where);
+
+/* Enqueue n fused stream-and-collide updates (alternating even/odd in-place
+ * passes).  Asynchronous. */
+int cnsf_step(cnsf_lattice* lat, int64_t n);
+
+/* Q_k = sum_i f_{k,i} of the current time level for z-planes [z0, z0+nzs),
+ * written FP64 to out (host or device) as [14][nzs][ny][nx]. */
+int cnsf_get_moments(cnsf_lattice* lat, double* out, int32_t z0, int32_t nzs, int32_t where);
+
+/* FP64 diagnostics of the current time level; flags: CNSF_DIAG_SUMS or
+ * CNSF_DIAG_SPECTRAL (adds eps_s, eps_d; allocates eight FP64 cell fields on
+ * first use, kept until cnsf_destroy). */
+int cnsf_diagnostics(cnsf_lattice* lat, int32_t flags, cnsf_diag* out);
+
+/* Step counter, parity and the byte size of an exported checkpoint. */
+int cnsf_get_info(const cnsf_lattice* lat, int64_t* step, int32_t* parity, size_t* checkpoint_bytes);
+
+/* Copy the raw stored populations (device -> host) with the parity and step;
+ * host buffer of checkpoint_bytes.  Import restores them into a lattice made
+ * from the same parameters (CNSF_E_SIZE otherwise). */
+int cnsf_export_populations(cnsf_lattice* lat, void* host, size_t bytes, int64_t* step, int32_t* parity);
+int cnsf_import_populations(cnsf_lattice* lat, const void* host, size_t bytes, int64_t step, int32_t parity);
+
+/* Plain device-to-device copy kernel of `bytes` (multiple of 16), used to
+ * measure the attainable HBM bandwidth next to the update. */
+int cnsf_hbm_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Kernel launch shape of the update: threads per block (64..256, multiple of
+ * 64; the kernels are compiled for at most 256) and whether block indices are remapped so that each XCD works on one
+ * contiguous span of cells. */
+int cnsf_set_launch(cnsf_lattice* lat, int32_t block, int32_t xcd_remap);
+
+const char* cnsf_last_error(void);
+const char* cnsf_status_string(int status);
+
+/* ------------------------------------------------------------------------
+ * Batched ensembles: many independent lattices (own size, parameters and
+ * populations) advanced by one launch per step over a descriptor table, the
+ * steps replayed from a captured HIP graph.  All members share the storage
+ * type and bc_x = PERIODIC.
+ */
+typedef struct cnsf_batch cnsf_batch;
+
+/* Create a batch of n members.  dev_buf / bytes as in cnsf_create, sized by
+ * cnsf_batch_required_bytes (NULL: library-allocated). */
+int cnsf_batch_required_bytes(const cnsf_params* members, int32_t n, size_t* bytes);
+int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size_t bytes, void* stream,
+                      cnsf_batch** out);
+int cnsf_batch_destroy(cnsf_batch* b);
+/* Member j's initial state (as cnsf_set_state, whole lattice). */
+int cnsf_batch_set_state(cnsf_batch* b, int32_t j, const double* Q, int32_t where);
+/* Advance every member by n steps.  mode 0: one launch per step over all
+ * members; mode 1: the same launches replayed from a HIP graph of
+ * `graph_steps` steps (captured on first use); mode 2: one launch per member
+ * per step (the sequential baseline). */
+int cnsf_batch_step(cnsf_batch* b, int64_t n, int32_t mode);
+int cnsf_batch_get_moments(cnsf_batch* b, int32_t j, double* out, int32_t where);
+/* Launch shape of the batched kernel: threads per block (64..256, multiple of
+ * 64), cells per tile
+ * (multiple of block), persistent grid size in blocks (0: one block per
+ * tile), and the number of steps captured per graph. */
+int cnsf_batch_set_launch(cnsf_batch* b, int32_t block, int32_t tile, int32_t grid, int32_t graph_steps);
+/* Time candidate launch shapes with HIP events and keep the fastest; results
+ * are cached in the JSON file `cache_path` (may be NULL) keyed by the batch's
+ * shape signature. */
+int cnsf_batch_autotune(cnsf_batch* b, const char* cache_path, int32_t steps_per_trial);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CNSF_H */

@@ -1,0 +1,460 @@
+// Batched ensembles: many independent periodic lattices advanced by one
+// launch per step.
+//
+// A descriptor table in device memory holds each member's geometry, constants
+// and population offset.  Each member's cells are cut into tiles of `tile`
+// cells; tile t belongs to the member whose prefix-summed first tile is the
+// largest one <= t (binary search, uniform per block).  With grid = 0 every
+// tile gets its own block; with grid > 0 a fixed grid strides over the tiles
+// (persistent within a step).  Steps can be captured once into a HIP graph
+// and replayed.  Mode 2 launches the single-lattice update per member, the
+// sequential baseline.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/cnsf.h"
+#include "api_common.h"
+#include "cnsf_impl.h"
+#include "launch.h"
+
+namespace cnsf {
+
+struct Member {
+  Geom g;
+  Phys ph;
+  Codec cd;
+  uint64_t pop_offset;  // elements from the batch base
+  uint32_t tile0;       // first tile of this member
+  uint32_t ntiles;
+};
+
+template <int ST>
+__global__ void __launch_bounds__(256) k_batch_update(typename Store<ST>::T* __restrict__ base,
+                                                      const Member* __restrict__ members, int nmembers,
+                                                      uint32_t total_tiles, uint32_t tile, int parity) {
+  for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+    // member of tile t (uniform): last m with tile0 <= t
+    int lo = 0, hi = nmembers - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (members[mid].tile0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const Member& M = members[lo];
+    const Geom g = M.g;
+    typename Store<ST>::T* pop = base + M.pop_offset;
+    const uint32_t first = (t - M.tile0) * tile;
+    for (uint32_t j = threadIdx.x; j < tile; j += blockDim.x) {
+      const uint32_t c = first + j;
+      if (c >= g.ncells) break;
+      const Nbr n = neighbours(c, g);
+      uint32_t off[NV];
+      stream_offsets<ST, 0>(g, n, parity, off);
+      float gv[NC][NV];
+      gather<ST, 0, float>(pop, g, M.cd, n, parity, off, gv);
+      update_cell(gv, M.cd, M.ph);
+      scatter<ST, 0>(pop, g, M.cd, n, parity, off, gv);
+    }
+  }
+}
+
+static hipError_t launch_batch(int storage, void* base, const Member* members, int n, uint32_t total_tiles,
+                               uint32_t tile, int block, int grid, int parity, hipStream_t s) {
+  const uint32_t nb = grid > 0 ? (uint32_t)grid : total_tiles;
+  if (storage == 0)
+    hipLaunchKernelGGL(k_batch_update<0>, dim3(nb), dim3(block), 0, s, (float*)base, members, n, total_tiles, tile,
+                       parity);
+  else if (storage == 1)
+    hipLaunchKernelGGL(k_batch_update<1>, dim3(nb), dim3(block), 0, s, (uint16_t*)base, members, n, total_tiles,
+                       tile, parity);
+  else
+    hipLaunchKernelGGL(k_batch_update<2>, dim3(nb), dim3(block), 0, s, (uint16_t*)base, members, n, total_tiles,
+                       tile, parity);
+  return hipGetLastError();
+}
+
+}  // namespace cnsf
+
+using namespace cnsf;
+
+struct cnsf_batch {
+  std::vector<cnsf_params> p;
+  std::vector<Member> m;   // host copy
+  std::vector<PhysD> phd;
+  Member* dm = nullptr;    // device table
+  int storage = 0;
+  void* base = nullptr;
+  bool owned = false;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;   // caller's stream
+  hipStream_t gstream = nullptr;  // capture stream of the graph
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int device = 0;
+  int parity = 0;
+  int64_t step = 0;
+  int block = 256;
+  uint32_t tile = 256;
+  int grid = 0;
+  int graph_steps = 20;
+  uint32_t total_tiles = 0;
+  int* dflag = nullptr;
+};
+
+static void batch_drop_graph(cnsf_batch* b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+}
+
+static int batch_retile(cnsf_batch* b) {
+  uint32_t t0 = 0;
+  for (auto& M : b->m) {
+    M.tile0 = t0;
+    M.ntiles = (M.g.ncells + b->tile - 1) / b->tile;
+    t0 += M.ntiles;
+  }
+  b->total_tiles = t0;
+  hipError_t e = hipMemcpy(b->dm, b->m.data(), sizeof(Member) * b->m.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "descriptor upload");
+  batch_drop_graph(b);
+  return CNSF_OK;
+}
+
+static hipError_t batch_launch_steps(cnsf_batch* b, int64_t n, hipStream_t s, int& parity) {
+  for (int64_t i = 0; i < n; ++i) {
+    hipError_t e = launch_batch(b->storage, b->base, b->dm, (int)b->m.size(), b->total_tiles, b->tile, b->block,
+                                b->grid, parity, s);
+    if (e != hipSuccess) return e;
+    parity ^= 1;
+  }
+  return hipSuccess;
+}
+
+extern "C" {
+
+int cnsf_batch_required_bytes(const cnsf_params* members, int32_t n, size_t* bytes) {
+  if (!members || n < 1 || !bytes) return fail(CNSF_E_INVALID, "batch needs n >= 1 members");
+  size_t tot = 0;
+  for (int j = 0; j < n; ++j) {
+    size_t nb = 0;
+    if (int e = cnsf_required_bytes(&members[j], &nb)) return e;
+    if (members[j].storage != members[0].storage) return fail(CNSF_E_INVALID, "members differ in storage");
+    if (members[j].bc_x != CNSF_BC_PERIODIC) return fail(CNSF_E_INVALID, "batch members must be periodic");
+    tot += (nb + 255) / 256 * 256;
+  }
+  *bytes = tot;
+  return CNSF_OK;
+}
+
+int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size_t bytes, void* stream,
+                      cnsf_batch** out) {
+  if (!out) return fail(CNSF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  if (int e = cnsf_batch_required_bytes(members, n, &need)) return e;
+  if (dev_buf && bytes < need) return fail(CNSF_E_NOMEM, "buffer of %zu bytes < required %zu", bytes, need);
+  if (dev_buf && ((uintptr_t)dev_buf & 255u)) return fail(CNSF_E_INVALID, "buffer not 256-byte aligned");
+  auto* b = new cnsf_batch();
+  b->storage = members[0].storage;
+  b->stream = (hipStream_t)stream;
+  b->bytes = need;
+  (void)hipGetDevice(&b->device);
+  uint64_t off = 0;
+  const size_t eb = elem_bytes(b->storage);
+  for (int j = 0; j < n; ++j) {
+    const cnsf_params* p = &members[j];
+    b->p.push_back(*p);
+    PhysD d = derive_phys_d(p);
+    b->phd.push_back(d);
+    Member M{};
+    M.g = derive_geom(p, d);
+    M.ph = to_float(d);
+    M.cd = derive_codec(p, d);
+    M.pop_offset = off;
+    size_t nb = 0;
+    cnsf_required_bytes(p, &nb);
+    off += (nb + 255) / 256 * 256 / eb;
+    b->m.push_back(M);
+  }
+  hipError_t e;
+  if (dev_buf) {
+    b->base = dev_buf;
+  } else {
+    e = hipMalloc(&b->base, need);
+    if (e != hipSuccess) {
+      delete b;
+      return fail(CNSF_E_NOMEM, "hipMalloc(%zu): %s", need, hipGetErrorString(e));
+    }
+    b->owned = true;
+  }
+  e = hipMalloc(&b->dm, sizeof(Member) * n);
+  if (e == hipSuccess) e = hipMalloc(&b->dflag, sizeof(int));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->gstream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    cnsf_batch_destroy(b);
+    return fail(CNSF_E_NOMEM, "batch buffers: %s", hipGetErrorString(e));
+  }
+  if (int r = batch_retile(b)) {
+    cnsf_batch_destroy(b);
+    return r;
+  }
+  *out = b;
+  return CNSF_OK;
+}
+
+int cnsf_batch_destroy(cnsf_batch* b) {
+  if (!b) return CNSF_OK;
+  (void)hipSetDevice(b->device);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->gstream) (void)hipStreamSynchronize(b->gstream);
+  batch_drop_graph(b);
+  if (b->owned && b->base) (void)hipFree(b->base);
+  if (b->dm) (void)hipFree(b->dm);
+  if (b->dflag) (void)hipFree(b->dflag);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->gstream) (void)hipStreamDestroy(b->gstream);
+  delete b;
+  return CNSF_OK;
+}
+
+int cnsf_batch_set_state(cnsf_batch* b, int32_t j, const double* Q, int32_t where) {
+  if (!b || !Q) return fail(CNSF_E_INVALID, "NULL argument");
+  if (j < 0 || j >= (int)b->m.size()) return fail(CNSF_E_INVALID, "member %d of %zu", j, b->m.size());
+  if (where != CNSF_HOST && where != CNSF_DEVICE) return fail(CNSF_E_INVALID, "where = %d", where);
+  if (b->parity != 0) return fail(CNSF_E_INVALID, "set_state on a batch at odd parity; set every member before stepping");
+  (void)hipSetDevice(b->device);
+  const Member& M = b->m[j];
+  const size_t qbytes = (size_t)NC * M.g.ncells * sizeof(double);
+  const double* dQ = Q;
+  double* tmp = nullptr;
+  hipError_t e = hipSuccess;
+  if (where == CNSF_HOST) {
+    e = hipMalloc(&tmp, qbytes);
+    if (e != hipSuccess) return fail(CNSF_E_NOMEM, "hipMalloc(%zu): %s", qbytes, hipGetErrorString(e));
+    e = hipMemcpyAsync(tmp, Q, qbytes, hipMemcpyHostToDevice, b->stream);
+    dQ = tmp;
+  }
+  int bad = 0;
+  void* pop = (char*)b->base + M.pop_offset * elem_bytes(b->storage);
+  if (e == hipSuccess) e = hipMemsetAsync(b->dflag, 0, sizeof(int), b->stream);
+  if (e == hipSuccess) e = launch_init(b->storage, pop, dQ, M.g, b->phd[j], M.cd, 0, M.g.ncells, b->dflag, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&bad, b->dflag, sizeof(int), hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "batch set_state");
+  if (bad) return fail(CNSF_E_STATE, "member %d: rho <= 0, p <= 0 or a non-finite value", j);
+  return CNSF_OK;
+}
+
+int cnsf_batch_set_launch(cnsf_batch* b, int32_t block, int32_t tile, int32_t grid, int32_t graph_steps) {
+  if (!b) return fail(CNSF_E_INVALID, "batch is NULL");
+  if (block < 64 || block > 256 || block % 64) return fail(CNSF_E_INVALID, "block %d not a multiple of 64 in [64, 256]", block);
+  if (tile < block || tile % block) return fail(CNSF_E_INVALID, "tile %d must be a multiple of block %d", tile, block);
+  if (grid < 0) return fail(CNSF_E_INVALID, "grid %d", grid);
+  if (graph_steps < 2 || graph_steps % 2) return fail(CNSF_E_INVALID, "graph_steps %d must be even >= 2", graph_steps);
+  b->block = block;
+  b->grid = grid;
+  b->graph_steps = graph_steps;
+  if ((uint32_t)tile != b->tile) {
+    b->tile = tile;
+    return batch_retile(b);
+  }
+  batch_drop_graph(b);
+  return CNSF_OK;
+}
+
+int cnsf_batch_step(cnsf_batch* b, int64_t n, int32_t mode) {
+  if (!b) return fail(CNSF_E_INVALID, "batch is NULL");
+  if (n < 0 || mode < 0 || mode > 2) return fail(CNSF_E_INVALID, "n %lld, mode %d", (long long)n, mode);
+  (void)hipSetDevice(b->device);
+  hipError_t e = hipSuccess;
+  if (mode == 2) {
+    for (int64_t s = 0; s < n && e == hipSuccess; ++s) {
+      for (size_t j = 0; j < b->m.size() && e == hipSuccess; ++j) {
+        const Member& M = b->m[j];
+        void* pop = (char*)b->base + M.pop_offset * elem_bytes(b->storage);
+        e = launch_update(b->storage, pop, M.g, M.ph, M.cd, b->parity, b->block, 1, b->stream);
+      }
+      b->parity ^= 1;
+    }
+  } else if (mode == 0) {
+    e = batch_launch_steps(b, n, b->stream, b->parity);
+  } else {
+    int64_t left = n;
+    // graphs start at even parity and hold an even number of steps
+    if (left > 0 && b->parity) {
+      e = batch_launch_steps(b, 1, b->stream, b->parity);
+      --left;
+    }
+    const int64_t reps = left / b->graph_steps;
+    if (e == hipSuccess && reps > 0) {
+      if (!b->gexec) {
+        hipGraph_t graph = nullptr;
+        int par = 0;
+        e = hipStreamBeginCapture(b->gstream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+          hipError_t el = batch_launch_steps(b, b->graph_steps, b->gstream, par);
+          e = hipStreamEndCapture(b->gstream, &graph);
+          if (el != hipSuccess) e = el;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      if (e == hipSuccess) e = hipEventRecord(b->ev_in, b->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->gstream, b->ev_in, 0);
+      for (int64_t r = 0; r < reps && e == hipSuccess; ++r) e = hipGraphLaunch(b->gexec, b->gstream);
+      if (e == hipSuccess) e = hipEventRecord(b->ev_out, b->gstream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, b->ev_out, 0);
+      left -= reps * b->graph_steps;
+    }
+    if (e == hipSuccess && left > 0) e = batch_launch_steps(b, left, b->stream, b->parity);
+  }
+  if (e != hipSuccess) return hip_fail(e, "batch step");
+  b->step += n;
+  return CNSF_OK;
+}
+
+int cnsf_batch_get_moments(cnsf_batch* b, int32_t j, double* out, int32_t where) {
+  if (!b || !out) return fail(CNSF_E_INVALID, "NULL argument");
+  if (j < 0 || j >= (int)b->m.size()) return fail(CNSF_E_INVALID, "member %d of %zu", j, b->m.size());
+  (void)hipSetDevice(b->device);
+  const Member& M = b->m[j];
+  const size_t qbytes = (size_t)NC * M.g.ncells * sizeof(double);
+  double* dst = out;
+  double* tmp = nullptr;
+  hipError_t e = hipSuccess;
+  if (where == CNSF_HOST) {
+    e = hipMalloc(&tmp, qbytes);
+    if (e != hipSuccess) return fail(CNSF_E_NOMEM, "hipMalloc(%zu): %s", qbytes, hipGetErrorString(e));
+    dst = tmp;
+  }
+  const void* pop = (const char*)b->base + M.pop_offset * elem_bytes(b->storage);
+  e = launch_moments(b->storage, pop, dst, M.g, M.cd, b->parity, 0, M.g.ncells, b->stream);
+  if (e == hipSuccess && tmp) e = hipMemcpyAsync(out, tmp, qbytes, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "batch get_moments");
+  return CNSF_OK;
+}
+
+// Shape signature of a batch: storage and the sorted member sizes.
+static std::string batch_signature(const cnsf_batch* b) {
+  std::vector<uint32_t> sizes;
+  for (const auto& M : b->m) sizes.push_back(M.g.ncells);
+  std::sort(sizes.begin(), sizes.end());
+  std::ostringstream os;
+  os << "s" << b->storage << "_n" << sizes.size();
+  uint64_t h = 1469598103934665603ull;
+  for (uint32_t s : sizes) {
+    h ^= s;
+    h *= 1099511628211ull;
+  }
+  os << "_" << std::hex << h;
+  return os.str();
+}
+
+static bool cache_lookup(const char* path, const std::string& key, int& block, int& tile, int& grid) {
+  if (!path) return false;
+  std::ifstream in(path);
+  if (!in) return false;
+  std::stringstream ss;
+  ss << in.rdbuf();
+  const std::string s = ss.str();
+  const size_t pos = s.find("\"" + key + "\"");
+  if (pos == std::string::npos) return false;
+  return sscanf(s.c_str() + pos + key.size() + 2, " : {\"block\": %d, \"tile\": %d, \"grid\": %d}", &block, &tile,
+                &grid) == 3;
+}
+
+static void cache_store(const char* path, const std::string& key, int block, int tile, int grid) {
+  if (!path) return;
+  std::string body;
+  {
+    std::ifstream in(path);
+    if (in) {
+      std::stringstream ss;
+      ss << in.rdbuf();
+      body = ss.str();
+    }
+  }
+  char entry[256];
+  snprintf(entry, sizeof entry, "\"%s\": {\"block\": %d, \"tile\": %d, \"grid\": %d}", key.c_str(), block, tile, grid);
+  const size_t close = body.rfind('}');
+  if (body.empty() || close == std::string::npos) {
+    body = std::string("{\n  ") + entry + "\n}\n";
+  } else {
+    const bool empty = body.find('"') == std::string::npos;
+    body = body.substr(0, close);
+    while (!body.empty() && (body.back() == '\n' || body.back() == ' ')) body.pop_back();
+    body += (empty ? "\n  " : ",\n  ") + std::string(entry) + "\n}\n";
+  }
+  std::ofstream out(path);
+  out << body;
+}
+
+int cnsf_batch_autotune(cnsf_batch* b, const char* cache_path, int32_t steps_per_trial) {
+  if (!b) return fail(CNSF_E_INVALID, "batch is NULL");
+  if (steps_per_trial < 2) steps_per_trial = 2;
+  steps_per_trial += steps_per_trial % 2;
+  (void)hipSetDevice(b->device);
+  const std::string key = batch_signature(b);
+  int bb, tt, gg;
+  if (cache_lookup(cache_path, key, bb, tt, gg)) return cnsf_batch_set_launch(b, bb, tt, gg, b->graph_steps);
+  // trial steps change the state: keep a copy and restore it afterwards
+  void* save = nullptr;
+  hipError_t e = hipMalloc(&save, b->bytes);
+  if (e != hipSuccess) return fail(CNSF_E_NOMEM, "autotune copy of %zu bytes: %s", b->bytes, hipGetErrorString(e));
+  e = hipMemcpyAsync(save, b->base, b->bytes, hipMemcpyDeviceToDevice, b->stream);
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device);
+  struct Cand { int block, tile, grid; };
+  std::vector<Cand> cands;
+  for (int blk : {64, 128, 256})
+    for (int mult : {1, 2, 4})
+      for (int grd : {0, ncu * 4, ncu * 8}) cands.push_back({blk, blk * mult, grd});
+  hipEvent_t t0, t1;
+  (void)hipEventCreate(&t0);
+  (void)hipEventCreate(&t1);
+  float best = 1e30f;
+  Cand bestc{b->block, (int)b->tile, b->grid};
+  const int parity0 = b->parity;
+  for (const Cand& c : cands) {
+    if (e != hipSuccess) break;
+    if (int r = cnsf_batch_set_launch(b, c.block, c.tile, c.grid, b->graph_steps)) { e = hipErrorInvalidValue; (void)r; break; }
+    int par = parity0;
+    e = batch_launch_steps(b, 2, b->stream, par);  // warm up
+    if (e == hipSuccess) e = hipEventRecord(t0, b->stream);
+    if (e == hipSuccess) e = batch_launch_steps(b, steps_per_trial, b->stream, par);
+    if (e == hipSuccess) e = hipEventRecord(t1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(t1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      bestc = c;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->base, save, b->bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  (void)hipFree(save);
+  b->parity = parity0;
+  if (e != hipSuccess) return hip_fail(e, "autotune");
+  if (int r = cnsf_batch_set_launch(b, bestc.block, bestc.tile, bestc.grid, b->graph_steps)) return r;
+  cache_store(cache_path, key, bestc.block, bestc.tile, bestc.grid);
+  return CNSF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,32 @@
+// Host-side launchers of the cnsf kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cnsf_impl.h"
+
+namespace cnsf {
+
+hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity, int block,
+                         int remap, hipStream_t s);
+hipError_t launch_init(int storage, void* pop, const double* Q, const Geom& g, const PhysD& ph, const Codec& cd,
+                       uint32_t cell0, uint32_t nslab, int* bad, hipStream_t s);
+hipError_t launch_moments(int storage, const void* pop, double* out, const Geom& g, const Codec& cd, int parity,
+                          uint32_t cell0, uint32_t nslab, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+// Diagnostics: FP64 sums and the spectral dissipation averages.
+struct DiagPartial {
+  double mass, mx, my, mz, energy, ek2;  // ek2 = sum rho |u|^2
+  double min_rho, min_p;
+  double sensor, nonfinite;
+  double eps_s, eps_d;                   // sums of mu |curl u|^2 and mu (div u)^2
+};
+constexpr int DIAG_BLOCKS = 2048;
+hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const Phys& ph, const PhysD& phd,
+                            const Codec& cd, int parity, DiagPartial* partials, double* fields, hipStream_t s);
+// fields: u, v, w, mu (4 * ncells doubles), then div, wx, wy, wz (4 * ncells).
+hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial* partials, hipStream_t s);
+hipError_t launch_diag_final(DiagPartial* partials, int nparts, DiagPartial* out, hipStream_t s);
+
+}  // namespace cnsf

@@ -1,0 +1,160 @@
+// Fused stream-and-collide update, state initialisation and moment readout.
+//
+// One thread owns one cell.  Populations live in 98 planes (component k,
+// slot i) of `plane` elements each, x fastest inside a plane, so a wavefront
+// of 64 consecutive cells reads 64 consecutive elements of every plane.  The
+// in-place AA pattern alternates an even pass (read and write the cell's own
+// slots) and an odd pass (read from and write to the six face neighbours), so
+// one array holds the whole lattice.
+#include "cnsf_impl.h"
+#include "launch.h"
+
+namespace cnsf {
+
+// Block index remap: hardware deals blocks round-robin over the 8 XCDs; this
+// gives XCD j one contiguous span of blocks so that the cache lines shared by
+// neighbouring blocks (the +-x halo of the odd pass) stay in one L2.
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t per = nb / 8u, rem = nb % 8u;
+  const uint32_t j = b % 8u, q = b / 8u;
+  return j * per + (j < rem ? j : rem) + q;
+}
+
+template <int ST, int BC>
+__global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restrict__ pop, const Geom g, const Phys ph,
+                                                 const Codec cd, int parity, int remap) {
+  uint32_t bid = blockIdx.x;
+  if (remap) bid = xcd_block(bid, gridDim.x);
+  const uint32_t c = bid * blockDim.x + threadIdx.x;
+  if (c >= g.ncells) return;
+  const Nbr n = neighbours(c, g);
+  uint32_t off[NV];
+  stream_offsets<ST, BC>(g, n, parity, off);
+  float gv[NC][NV];
+  gather<ST, BC, float>(pop, g, cd, n, parity, off, gv);
+  update_cell(gv, cd, ph);
+  scatter<ST, BC>(pop, g, cd, n, parity, off, gv);
+}
+
+// f = f^eq(Q) for cells of z-planes [z0, z0 + nzs); FP64 arithmetic.
+template <int ST>
+__global__ void k_init(typename Store<ST>::T* __restrict__ pop, const double* __restrict__ Q, const Geom g,
+                       const PhysD ph, const Codec cd, uint32_t cell0, uint32_t nslab, int* __restrict__ bad) {
+  using S = Store<ST>;
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nslab) return;
+  const uint32_t c = cell0 + j;
+  double q[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) q[k] = Q[(uint64_t)k * nslab + j];
+  Prim<double> P = primitives<double>(q, ph);
+  bool ok = P.rho > 0.0 && P.p > 0.0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) ok = ok && isfinite(q[k]);
+  if (!ok) atomicOr(bad, 1);
+  double feq[NC][NV];
+  equilibrium_all<double>(q, P, ph.four_over_lam, feq);
+  const uint64_t cstride = (uint64_t)NV * g.plane;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    typename S::T* base = pop + (uint64_t)i * g.plane + c;
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+      base[k * cstride] = S::enc((float)((feq[k][i] - feq_ref<double>(cd, k, i)) * (double)cd.inv_scale[k]));
+  }
+}
+
+// Q_k = sum_i f_{k,i} of the current time level (FP64 accumulation).
+template <int ST, int BC>
+__global__ void k_moments(const typename Store<ST>::T* __restrict__ pop, double* __restrict__ out, const Geom g,
+                          const Codec cd, int parity, uint32_t cell0, uint32_t nslab) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nslab) return;
+  const Nbr n = neighbours(cell0 + j, g);
+  uint32_t off[NV];
+  stream_offsets<ST, BC>(g, n, parity, off);
+  double gv[NC][NV];
+  gather<ST, BC, double>(pop, g, cd, n, parity, off, gv);
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s += gv[k][i];
+    out[(uint64_t)k * nslab + j] = q_ref<double>(cd, k) + s;
+  }
+}
+
+__global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n16) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ launchers
+template <int ST, int BC>
+static hipError_t launch_update_t(void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity, int block,
+                                  int remap, hipStream_t s) {
+  const uint32_t nb = (g.ncells + block - 1) / block;
+  hipLaunchKernelGGL((k_update<ST, BC>), dim3(nb), dim3(block), 0, s, (typename Store<ST>::T*)pop, g, ph, cd, parity,
+                     remap);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity, int block,
+                         int remap, hipStream_t s) {
+#define CNSF_CASE(ST, BC) \
+  if (storage == ST && g.bc_x == BC) return launch_update_t<ST, BC>(pop, g, ph, cd, parity, block, remap, s);
+  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2)
+  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2)
+  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2)
+#undef CNSF_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_init(int storage, void* pop, const double* Q, const Geom& g, const PhysD& ph, const Codec& cd,
+                       uint32_t cell0, uint32_t nslab, int* bad, hipStream_t s) {
+  const int block = 256;
+  const uint32_t nb = (nslab + block - 1) / block;
+  if (nb == 0) return hipSuccess;
+  if (storage == 0)
+    hipLaunchKernelGGL(k_init<0>, dim3(nb), dim3(block), 0, s, (float*)pop, Q, g, ph, cd, cell0, nslab, bad);
+  else if (storage == 1)
+    hipLaunchKernelGGL(k_init<1>, dim3(nb), dim3(block), 0, s, (uint16_t*)pop, Q, g, ph, cd, cell0, nslab, bad);
+  else
+    hipLaunchKernelGGL(k_init<2>, dim3(nb), dim3(block), 0, s, (uint16_t*)pop, Q, g, ph, cd, cell0, nslab, bad);
+  return hipGetLastError();
+}
+
+template <int ST, int BC>
+static hipError_t launch_moments_t(const void* pop, double* out, const Geom& g, const Codec& cd, int parity,
+                                   uint32_t cell0, uint32_t nslab, hipStream_t s) {
+  const int block = 256;
+  const uint32_t nb = (nslab + block - 1) / block;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_moments<ST, BC>), dim3(nb), dim3(block), 0, s, (const typename Store<ST>::T*)pop, out, g, cd,
+                     parity, cell0, nslab);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(int storage, const void* pop, double* out, const Geom& g, const Codec& cd, int parity,
+                          uint32_t cell0, uint32_t nslab, hipStream_t s) {
+#define CNSF_CASE(ST, BC) \
+  if (storage == ST && g.bc_x == BC) return launch_moments_t<ST, BC>(pop, out, g, cd, parity, cell0, nslab, s);
+  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2)
+  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2)
+  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2)
+#undef CNSF_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  const uint64_t n16 = bytes / 16;
+  int dev = 0, ncu = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint64_t want = (n16 + 255) / 256;
+  const uint32_t nb = (uint32_t)(want < (uint64_t)ncu * 32 ? (want ? want : 1) : (uint64_t)ncu * 32);
+  hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
+  return hipGetLastError();
+}
+
+}  // namespace cnsf

@@ -1,0 +1,294 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (the FP32 bound of 1e-5 relative L2 on rho, u and T after 100
+steps, and 2e-3 for the FP16-deviation storage) are the targets the method is
+held to here; every comparison is element by element on the same seeded
+inputs.  Sizes span several 256-cell blocks with a ragged tail.
+"""
+import os
+import sys
+import warnings
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import diagnostics as odiag
+from oracle import lbm
+
+pytestmark = pytest.mark.gpu
+warnings.simplefilter("ignore", RuntimeWarning)
+
+
+def _cnsf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_13437_amd as cnsf
+    cnsf.library()
+    return cnsf
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def fields(Q, prm):
+    rho, u, E, p, T = lbm.primitives(Q, prm)
+    return dict(rho=rho, u=u, T=T)
+
+
+def compare(Qg, Qo, prm):
+    fg, fo = fields(Qg, prm), fields(Qo, prm)
+    return {k: rel_l2(fg[k], fo[k]) for k in fg}
+
+
+def run_gpu(case, steps, *, storage=None, block=256, remap=True):
+    cnsf = _cnsf()
+    prm = dict(case.params)
+    if storage is not None:
+        prm["storage"] = storage
+    L = cnsf.Lattice(prm)
+    L.set_launch(block, remap)
+    L.set_state(case.Q0)
+    L.step(steps)
+    Q = L.moments()
+    return L, Q
+
+
+def run_oracle(case, steps):
+    return lbm.moments(lbm.run(case.Q0, case.params, steps))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+# ------------------------------------------------------------------ FP32 parity
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_ragged_fp32(seed):
+    case = W.random_case(13, 11, 9, seed=seed, sensor=True, amp=0.5)
+    n = 20
+    log(f"case {case.name} steps {n}")
+    _, Qg = run_gpu(case, n)
+    Qo = run_oracle(case, n)
+    err = compare(Qg, Qo, case.params)
+    log(f"  rel L2 {err}")
+    assert all(v < 1e-5 for v in err.values()), err
+
+
+def test_smooth_100_steps_fp32():
+    case = W.smooth_random_case(24, 20, 16, seed=3, sensor=True)
+    log(f"case {case.name}")
+    _, Qg = run_gpu(case, 100)
+    Qo = run_oracle(case, 100)
+    err = compare(Qg, Qo, case.params)
+    log(f"  rel L2 {err}")
+    assert all(v < 1e-5 for v in err.values()), err
+
+
+@pytest.mark.parametrize("n", [100, 101])
+def test_tgv32_fp32(n):
+    """Taylor-Green at 32^3; an odd step count reads moments at odd parity."""
+    case = W.tgv(32)
+    log(f"case tgv32 steps {n}")
+    _, Qg = run_gpu(case, n)
+    Qo = run_oracle(case, n)
+    err = compare(Qg, Qo, case.params)
+    log(f"  rel L2 {err}")
+    assert all(v < 1e-5 for v in err.values()), err
+
+
+@pytest.mark.parametrize("n", [100, 500])
+def test_sod_walls_fp32(n):
+    """Sod tube 256 x 4 x 4 between parity walls, sensor active at the shock."""
+    case = W.sod(256, 4, 4)
+    log(f"case sod256x4x4 steps {n}")
+    _, Qg = run_gpu(case, n)
+    c1 = W.sod(256, 1, 1)
+    Qo1 = run_oracle(c1, n)
+    Qo = np.broadcast_to(Qo1, Qg.shape)
+    err = compare(Qg, Qo, case.params)
+    log(f"  rel L2 {err}")
+    assert all(v < 1e-5 for v in err.values()), err
+
+
+def test_becker_equilibrium_ends_fp32():
+    case = W.becker(128, 4, 4)
+    n = 400
+    log(f"case becker128x4x4 steps {n}")
+    _, Qg = run_gpu(case, n)
+    c1 = W.becker(128, 1, 1)
+    Qo = np.broadcast_to(run_oracle(c1, n), Qg.shape)
+    err = compare(Qg, Qo, case.params)
+    log(f"  rel L2 {err}")
+    assert all(v < 1e-5 for v in err.values()), err
+
+
+@pytest.mark.parametrize("block,remap", [(64, False), (128, True), (192, True), (256, False)])
+def test_launch_shapes_bitwise_equal(block, remap):
+    case = W.random_case(13, 11, 9, seed=5, sensor=True, amp=0.5)
+    log(f"case {case.name} block {block} remap {remap}")
+    _, Qa = run_gpu(case, 7, block=256, remap=True)
+    _, Qb = run_gpu(case, 7, block=block, remap=remap)
+    assert np.array_equal(Qa, Qb)
+
+
+def test_launch_shape_beyond_compiled_bound_rejected():
+    cnsf = _cnsf()
+    case = W.random_case(8, 8, 8, seed=5)
+    L = cnsf.Lattice(case.params)
+    with pytest.raises(cnsf.CnsfError) as e:
+        L.set_launch(512, True)
+    assert e.value.status == cnsf.CNSF_E_INVALID
+
+
+# ------------------------------------------------------------------ diagnostics
+def test_diagnostics_match_oracle_on_same_state():
+    cnsf = _cnsf()
+    case = W.tgv(32)
+    log("case tgv32 diagnostics")
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    d0 = L.diagnostics(spectral=True)
+    o0 = odiag.diagnostics(case.Q0, case.params)
+    assert abs(d0["E_k"] - 0.125) < 1e-7
+    assert abs(d0["eps_s"] - 0.75 * case.params["mu0"]) < 1e-9
+    L.step(40)
+    d = L.diagnostics(spectral=True)
+    o = odiag.diagnostics(L.moments(), case.params)
+    log(f"  gpu {d}\n  oracle {o}")
+    for k in ("mass", "energy", "E_k", "eps_s", "eps_d", "min_rho", "min_p"):
+        assert abs(d[k] - o[k]) <= 1e-9 * max(abs(o[k]), 1e-12), k
+    for a in range(3):
+        assert abs(d["momentum"][a] - o["momentum"][a]) < 1e-9
+
+
+def test_diagnostics_non_power_of_two_axes():
+    cnsf = _cnsf()
+    case = W.smooth_random_case(24, 20, 12, seed=9, sensor=False)
+    log("case smooth24x20x12 diagnostics")
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    L.step(5)
+    d = L.diagnostics(spectral=True)
+    o = odiag.diagnostics(L.moments(), case.params)
+    for k in ("E_k", "eps_s", "eps_d"):
+        assert abs(d[k] - o[k]) <= 1e-9 * max(abs(o[k]), 1e-12), (k, d[k], o[k])
+
+
+def test_conservation_on_gpu():
+    cnsf = _cnsf()
+    case = W.tgv(32)
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    d0 = L.diagnostics(spectral=False)
+    L.step(200)
+    d1 = L.diagnostics(spectral=False)
+    assert abs(d1["mass"] - d0["mass"]) < 1e-6 * d0["mass"]
+    assert abs(d1["energy"] - d0["energy"]) < 1e-6 * d0["energy"]
+    assert d1["nonfinite"] == 0
+
+
+# ------------------------------------------------------------------ state handling
+def test_checkpoint_roundtrip_bitwise():
+    cnsf = _cnsf()
+    case = W.random_case(13, 11, 9, seed=6, sensor=True, amp=0.5)
+    A = cnsf.Lattice(case.params)
+    A.set_state(case.Q0)
+    A.step(31)
+    buf, step, parity = A.export_populations()
+    A.step(20)
+    B = cnsf.Lattice(case.params)
+    B.import_populations(buf, step, parity)
+    B.step(20)
+    assert np.array_equal(A.moments(), B.moments())
+    assert B.info()[0] == 51 and B.info()[1] == 1
+
+
+def test_set_state_rejects_nonphysical():
+    cnsf = _cnsf()
+    case = W.random_case(8, 8, 8, seed=7)
+    L = cnsf.Lattice(case.params)
+    Q = case.Q0.copy()
+    Q[0, 3, 2, 1] = -1.0
+    with pytest.raises(cnsf.CnsfError) as e:
+        L.set_state(Q)
+    assert e.value.status == cnsf.CNSF_E_STATE
+    Q = case.Q0.copy()
+    Q[4, 0, 0, 0] = np.nan
+    with pytest.raises(cnsf.CnsfError):
+        L.set_state(Q)
+
+
+def test_slab_set_state_and_moments():
+    cnsf = _cnsf()
+    case = W.tgv(16)
+    L = cnsf.Lattice(case.params)
+    for z0 in range(0, 16, 5):
+        L.set_state(case.Q0[:, z0:z0 + 5], z0=z0)
+    L.step(3)
+    full = L.moments()
+    part = np.concatenate([L.moments(z0, min(4, 16 - z0)) for z0 in range(0, 16, 4)], axis=1)
+    assert np.array_equal(full, part)
+    Qo = run_oracle(case, 3)
+    assert rel_l2(full, Qo) < 1e-6
+
+
+# ------------------------------------------------------------------ compressed storage
+@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP16, 2e-3), (W.STORAGE_BF16, None)])
+def test_compressed_storage_error(storage, bound):
+    case = W.tgv(32)
+    n = 100
+    log(f"case tgv32 storage {storage}")
+    _, Qg = run_gpu(case, n, storage=storage)
+    Qo = run_oracle(case, n)
+    err = compare(Qg, Qo, case.params)
+    log(f"  storage {storage} rel L2 {err}")
+    assert all(np.isfinite(v) for v in err.values())
+    if bound is not None:
+        assert all(v < bound for v in err.values()), err
+
+
+# ------------------------------------------------------------------ batch
+def test_batch_matches_single_lattices():
+    cnsf = _cnsf()
+    cases = [W.tgv(32, M0=0.8), W.tgv(24, M0=0.8), W.random_case(13, 11, 9, seed=8, sensor=True, amp=0.5)]
+    for c in cases:
+        c.params["storage"] = W.STORAGE_FP16
+    prms = [c.params for c in cases]
+    n = 22
+    ref = []
+    for c in cases:
+        L = cnsf.Lattice(c.params)
+        L.set_state(c.Q0)
+        L.step(n)
+        ref.append(L.moments())
+        assert np.all(np.isfinite(ref[-1]))
+    for mode in (0, 1, 2):
+        for (block, tile, grid) in ((256, 256, 0), (128, 512, 64)):
+            log(f"batch mode {mode} block {block} tile {tile} grid {grid}")
+            B = cnsf.Batch(prms)
+            B.set_launch(block, tile, grid, graph_steps=4)
+            for j, c in enumerate(cases):
+                B.set_state(j, c.Q0)
+            B.step(n, mode=mode)
+            for j in range(len(cases)):
+                assert np.array_equal(B.moments(j), ref[j]), (mode, j)
+            B.close()
+
+
+def test_batch_autotune_restores_state(tmp_path):
+    cnsf = _cnsf()
+    cases = [W.tgv(32), W.tgv(24, M0=0.8)]
+    B = cnsf.Batch([c.params for c in cases])
+    for j, c in enumerate(cases):
+        B.set_state(j, c.Q0)
+    before = [B.moments(j) for j in range(2)]
+    cache = str(tmp_path / "tune.json")
+    B.autotune(cache, steps_per_trial=4)
+    after = [B.moments(j) for j in range(2)]
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))
+    assert os.path.exists(cache)
+    B.autotune(cache, steps_per_trial=4)   # cache hit

@@ -1,0 +1,105 @@
+"""The C-ABI library loads, exports every declared entry point, agrees with the
+binding's struct layout and validates parameters, all without a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+import textwrap
+
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cnsf.h")
+
+
+@pytest.fixture(scope="module")
+def cnsf():
+    import paper_2608_13437_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_2608_13437_amd import build
+        build.build()
+    m.library()
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(cnsf_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(cnsf):
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(cnsf.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layout_matches_header(cnsf, tmp_path):
+    fields = [f for f, _ in cnsf.cnsf_params._fields_]
+    src = tmp_path / "layout.c"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "cnsf.h"', "int main(void) {",
+             '  printf("%zu\\n", sizeof(cnsf_params));',
+             '  printf("%zu\\n", sizeof(cnsf_diag));']
+    lines += [f'  printf("%zu\\n", offsetof(cnsf_params, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert out[0] == ctypes.sizeof(cnsf.cnsf_params)
+    assert out[1] == ctypes.sizeof(cnsf.cnsf_diag)
+    for f, off in zip(fields, out[2:]):
+        assert getattr(cnsf.cnsf_params, f).offset == off, f
+
+
+def test_params_default_and_bytes(cnsf):
+    p = cnsf.cnsf_params_default()
+    assert p.size == ctypes.sizeof(cnsf.cnsf_params)
+    q = cnsf.make_params(W.tgv_params(512))
+    n = cnsf.cnsf_required_bytes(q)
+    assert n == 98 * 512 ** 3 * 4
+    q.storage = W.STORAGE_FP16
+    assert cnsf.cnsf_required_bytes(q) == 98 * 512 ** 3 * 2
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("dt", 0.0), ("dx", -1.0), ("gamma", 1.0), ("tau_R", 0.0), ("tau_q", -1.0),
+    ("omega_min", 0.0), ("omega_min", 2.5), ("tau_base_override", 0.4), ("f_mu", -1.0),
+    ("visc_law", 7), ("bc_x", 5), ("storage", 3), ("C_sigma", -1.0), ("prandtl", 0.0),
+])
+def test_invalid_parameters_rejected(cnsf, field, value):
+    prm = W.tgv_params(16)
+    prm[field] = value
+    with pytest.raises(cnsf.CnsfError) as e:
+        cnsf.cnsf_required_bytes(cnsf.make_params(prm))
+    assert e.value.status == cnsf.CNSF_E_INVALID
+
+
+def test_subcharacteristic_bound_and_reference_state(cnsf):
+    prm = W.tgv_params(16)
+    prm["a_ref"] = 0.51 * prm["dx"] / prm["dt"]
+    with pytest.raises(cnsf.CnsfError):
+        cnsf.cnsf_required_bytes(cnsf.make_params(prm))
+    prm = W.tgv_params(16)
+    prm["Q_ref"] = list(prm["Q_ref"])
+    prm["Q_ref"][1] = 0.3   # a moving reference state is not supported
+    with pytest.raises(cnsf.CnsfError):
+        cnsf.cnsf_required_bytes(cnsf.make_params(prm))
+    prm = W.tgv_params(16)
+    prm["C_sigma"], prm["mu0"] = 10.0, 0.0
+    with pytest.raises(cnsf.CnsfError):
+        cnsf.cnsf_required_bytes(cnsf.make_params(prm))
+
+
+def test_lattice_too_large_for_32bit_offsets(cnsf):
+    prm = W.default_params(1024, 1024, 1024)
+    with pytest.raises(cnsf.CnsfError):
+        cnsf.cnsf_required_bytes(cnsf.make_params(prm))
+
+
+def test_status_strings(cnsf):
+    assert cnsf.cnsf_status_string(0) == "ok"
+    assert "HIP" in cnsf.cnsf_status_string(3)
