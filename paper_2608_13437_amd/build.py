@@ -22,7 +22,9 @@ HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions in the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-munsafe-fp-atomics",
+    # fuse multiply-add only inside one source expression, so that every
+    # kernel that inlines the same cell update rounds it the same way
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -159,6 +159,7 @@ Codec derive_codec(const cnsf_params* p, const PhysD& ph) {
     const double s = p->storage_scale[k] > 0.0 ? p->storage_scale[k] : 1.0;
     cd.scale[k] = (float)s;
     cd.inv_scale[k] = (float)(1.0 / s);
+    if (s != 1.0 && p->storage != CNSF_STORAGE_FP32) cd.scaled = 1;
   }
   return cd;
 }

@@ -36,7 +36,7 @@ struct Member {
   uint32_t ntiles;
 };
 
-template <int ST>
+template <int ST, bool SC>
 __global__ void __launch_bounds__(256) k_batch_update(typename Store<ST>::T* __restrict__ base,
                                                       const Member* __restrict__ members, int nmembers,
                                                       uint32_t total_tiles, uint32_t tile, int parity) {
@@ -59,26 +59,29 @@ __global__ void __launch_bounds__(256) k_batch_update(typename Store<ST>::T* __r
       uint32_t off[NV];
       stream_offsets<ST, 0>(g, n, parity, off);
       float gv[NC][NV];
-      gather<ST, 0, float>(pop, g, M.cd, n, parity, off, gv);
+      gather<ST, 0, SC, float>(pop, g, M.cd, n, parity, off, gv);
       update_cell(gv, M.cd, M.ph);
-      scatter<ST, 0>(pop, g, M.cd, n, parity, off, gv);
+      scatter<ST, 0, SC>(pop, g, M.cd, n, parity, off, gv);
     }
   }
 }
 
-static hipError_t launch_batch(int storage, void* base, const Member* members, int n, uint32_t total_tiles,
-                               uint32_t tile, int block, int grid, int parity, hipStream_t s) {
+static hipError_t launch_batch(int storage, bool scaled, void* base, const Member* members, int n,
+                               uint32_t total_tiles, uint32_t tile, int block, int grid, int parity, hipStream_t s) {
   const uint32_t nb = grid > 0 ? (uint32_t)grid : total_tiles;
-  if (storage == 0)
-    hipLaunchKernelGGL(k_batch_update<0>, dim3(nb), dim3(block), 0, s, (float*)base, members, n, total_tiles, tile,
-                       parity);
-  else if (storage == 1)
-    hipLaunchKernelGGL(k_batch_update<1>, dim3(nb), dim3(block), 0, s, (uint16_t*)base, members, n, total_tiles,
-                       tile, parity);
-  else
-    hipLaunchKernelGGL(k_batch_update<2>, dim3(nb), dim3(block), 0, s, (uint16_t*)base, members, n, total_tiles,
-                       tile, parity);
-  return hipGetLastError();
+#define CNSF_CASE(ST, SC, T)                                                                                    \
+  if (storage == ST && scaled == SC) {                                                                          \
+    hipLaunchKernelGGL((k_batch_update<ST, SC>), dim3(nb), dim3(block), 0, s, (T*)base, members, n, total_tiles, \
+                       tile, parity);                                                                           \
+    return hipGetLastError();                                                                                   \
+  }
+  CNSF_CASE(0, false, float)
+  CNSF_CASE(1, false, uint16_t)
+  CNSF_CASE(2, false, uint16_t)
+  CNSF_CASE(1, true, uint16_t)
+  CNSF_CASE(2, true, uint16_t)
+#undef CNSF_CASE
+  return hipErrorInvalidValue;
 }
 
 }  // namespace cnsf
@@ -107,6 +110,7 @@ struct cnsf_batch {
   int graph_steps = 20;
   uint32_t total_tiles = 0;
   int* dflag = nullptr;
+  bool scaled = false;   // some member stores with a non-unit scale
 };
 
 static void batch_drop_graph(cnsf_batch* b) {
@@ -130,8 +134,8 @@ static int batch_retile(cnsf_batch* b) {
 
 static hipError_t batch_launch_steps(cnsf_batch* b, int64_t n, hipStream_t s, int& parity) {
   for (int64_t i = 0; i < n; ++i) {
-    hipError_t e = launch_batch(b->storage, b->base, b->dm, (int)b->m.size(), b->total_tiles, b->tile, b->block,
-                                b->grid, parity, s);
+    hipError_t e = launch_batch(b->storage, b->scaled, b->base, b->dm, (int)b->m.size(), b->total_tiles, b->tile,
+                                b->block, b->grid, parity, s);
     if (e != hipSuccess) return e;
     parity ^= 1;
   }
@@ -179,6 +183,7 @@ int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size
     M.ph = to_float(d);
     M.cd = derive_codec(p, d);
     M.pop_offset = off;
+    if (M.cd.scaled) b->scaled = true;
     size_t nb = 0;
     cnsf_required_bytes(p, &nb);
     off += (nb + 255) / 256 * 256 / eb;

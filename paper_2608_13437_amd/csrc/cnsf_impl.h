@@ -68,6 +68,7 @@ struct Codec {
   float KT_ref;   // (K_q T)_ref
   float scale[NC];
   float inv_scale[NC];
+  int32_t scaled;  // some s_k != 1: the kernels multiply by s_k / 1/s_k
 };
 
 // f^eq_{k,i}(Q_ref) (k, i compile-time after unrolling).
@@ -105,15 +106,10 @@ struct Store<1> {  // IEEE binary16, round to nearest even
   __device__ static inline uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
 };
 template <>
-struct Store<2> {  // bfloat16, round to nearest even
+struct Store<2> {  // bfloat16, round to nearest even (native conversion on gfx950)
   using T = uint16_t;
   __device__ static inline float dec(uint16_t v) { return __uint_as_float(((uint32_t)v) << 16); }
-  __device__ static inline uint16_t enc(float x) {
-    uint32_t b = __float_as_uint(x);
-    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (uint16_t)((b >> 16) | 0x40u);  // NaN stays NaN
-    b += 0x7fffu + ((b >> 16) & 1u);
-    return (uint16_t)(b >> 16);
-  }
+  __device__ static inline uint16_t enc(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 };
 
 // ------------------------------------------------------------------ D3Q7
@@ -443,7 +439,7 @@ __device__ inline void stream_offsets(const Geom& g, const Nbr& n, int parity, u
 // shift is mirror-symmetric in x, so the shifted value simply changes sign
 // for the x-odd components.  At an equilibrium end the link is the end
 // state's equilibrium.
-template <int ST, int BC, typename R>
+template <int ST, int BC, bool SC, typename R>
 __device__ inline void gather(const typename Store<ST>::T* __restrict__ pop, const Geom& g, const Codec& cd,
                               const Nbr& n, int parity, const uint32_t off[NV], R gv[NC][NV]) {
 #pragma unroll
@@ -452,7 +448,7 @@ __device__ inline void gather(const typename Store<ST>::T* __restrict__ pop, con
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       R v = (R)buf_load<ST>(rs, off[i]);
-      if (ST != 0) v *= (R)cd.scale[k];
+      if (ST != 0 && SC) v *= (R)cd.scale[k];
       if (crossed_end<BC>(g, n, parity, i)) {
         if (BC == 1 && x_odd(k)) v = -v;
         if (BC == 2) v = (R)(i == 1 ? g.dev_left[k] : g.dev_right[k]);
@@ -465,7 +461,7 @@ __device__ inline void gather(const typename Store<ST>::T* __restrict__ pop, con
 // Write g*_i to off[opp(i)] (see stream_offsets).  A link leaving through an
 // x-end is stored back into the cell as the opposite direction: mirrored at a
 // wall, replaced by the end state's equilibrium at an equilibrium end.
-template <int ST, int BC>
+template <int ST, int BC, bool SC>
 __device__ inline void scatter(typename Store<ST>::T* __restrict__ pop, const Geom& g, const Codec& cd, const Nbr& n,
                                int parity, const uint32_t off[NV], const float gv[NC][NV]) {
 #pragma unroll
@@ -478,7 +474,7 @@ __device__ inline void scatter(typename Store<ST>::T* __restrict__ pop, const Ge
         if (BC == 1 && x_odd(k)) v = -v;
         if (BC == 2) v = (i == 2) ? g.dev_left[k] : g.dev_right[k];
       }
-      if (ST != 0) v *= cd.inv_scale[k];
+      if (ST != 0 && SC) v *= cd.inv_scale[k];
       buf_store<ST>(rs, off[opp(i)], v);
     }
   }

@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* _
     uint32_t off[NV];
     stream_offsets<ST, BC>(g, n, parity, off);
     double gv[NC][NV];
-    gather<ST, BC, double>(pop, g, cd, n, parity, off, gv);
+    gather<ST, BC, true, double>(pop, g, cd, n, parity, off, gv);
     double Q[NC];
     bool finite = true;
 #pragma unroll

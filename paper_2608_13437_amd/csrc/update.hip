@@ -20,7 +20,7 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
   return j * per + (j < rem ? j : rem) + q;
 }
 
-template <int ST, int BC>
+template <int ST, int BC, bool SC>
 __global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restrict__ pop, const Geom g, const Phys ph,
                                                  const Codec cd, int parity, int remap) {
   uint32_t bid = blockIdx.x;
@@ -31,9 +31,9 @@ __global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restric
   uint32_t off[NV];
   stream_offsets<ST, BC>(g, n, parity, off);
   float gv[NC][NV];
-  gather<ST, BC, float>(pop, g, cd, n, parity, off, gv);
+  gather<ST, BC, SC, float>(pop, g, cd, n, parity, off, gv);
   update_cell(gv, cd, ph);
-  scatter<ST, BC>(pop, g, cd, n, parity, off, gv);
+  scatter<ST, BC, SC>(pop, g, cd, n, parity, off, gv);
 }
 
 // f = f^eq(Q) for cells of z-planes [z0, z0 + nzs); FP64 arithmetic.
@@ -74,7 +74,7 @@ __global__ void k_moments(const typename Store<ST>::T* __restrict__ pop, double*
   uint32_t off[NV];
   stream_offsets<ST, BC>(g, n, parity, off);
   double gv[NC][NV];
-  gather<ST, BC, double>(pop, g, cd, n, parity, off, gv);
+  gather<ST, BC, true, double>(pop, g, cd, n, parity, off, gv);
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     double s = 0.0;
@@ -84,28 +84,40 @@ __global__ void k_moments(const typename Store<ST>::T* __restrict__ pop, double*
   }
 }
 
-__global__ void k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n16) {
+// Plain copy, 4 x 16 bytes in flight per thread per iteration.
+__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n16) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
 }
 
 // ------------------------------------------------------------------ launchers
-template <int ST, int BC>
+template <int ST, int BC, bool SC>
 static hipError_t launch_update_t(void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity, int block,
                                   int remap, hipStream_t s) {
   const uint32_t nb = (g.ncells + block - 1) / block;
-  hipLaunchKernelGGL((k_update<ST, BC>), dim3(nb), dim3(block), 0, s, (typename Store<ST>::T*)pop, g, ph, cd, parity,
-                     remap);
+  hipLaunchKernelGGL((k_update<ST, BC, SC>), dim3(nb), dim3(block), 0, s, (typename Store<ST>::T*)pop, g, ph, cd,
+                     parity, remap);
   return hipGetLastError();
 }
 
 hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity, int block,
                          int remap, hipStream_t s) {
-#define CNSF_CASE(ST, BC) \
-  if (storage == ST && g.bc_x == BC) return launch_update_t<ST, BC>(pop, g, ph, cd, parity, block, remap, s);
-  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2)
-  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2)
-  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2)
+  const bool sc = cd.scaled != 0;
+#define CNSF_CASE(ST, BC, SC) \
+  if (storage == ST && g.bc_x == BC && sc == SC) return launch_update_t<ST, BC, SC>(pop, g, ph, cd, parity, block, remap, s);
+  CNSF_CASE(0, 0, false) CNSF_CASE(0, 1, false) CNSF_CASE(0, 2, false)
+  CNSF_CASE(1, 0, false) CNSF_CASE(1, 1, false) CNSF_CASE(1, 2, false)
+  CNSF_CASE(2, 0, false) CNSF_CASE(2, 1, false) CNSF_CASE(2, 2, false)
+  CNSF_CASE(1, 0, true) CNSF_CASE(1, 1, true) CNSF_CASE(1, 2, true)
+  CNSF_CASE(2, 0, true) CNSF_CASE(2, 1, true) CNSF_CASE(2, 2, true)
 #undef CNSF_CASE
   return hipErrorInvalidValue;
 }
