@@ -186,11 +186,11 @@ def main():
     res = {}
     for st in storages:
         L, prm = load_lattice_tgv(cnsf, n, st)
-        L.set_launch(256, True)
+        launch = L.get_launch()
         mean_ms, min_ms, wall = time_update(L, args.steps, args.warmup)
         d = L.diagnostics(spectral=False)
         alg_bytes = 98 * 2 * BYTES_PER_POP[st] * cells
-        res[st] = dict(ms=mean_ms, min_ms=min_ms, wall=wall, mlups=cells / (mean_ms * 1e-3) / 1e6,
+        res[st] = dict(ms=mean_ms, min_ms=min_ms, wall=wall, mlups=cells / (mean_ms * 1e-3) / 1e6, launch=launch,
                        gbps=alg_bytes / (mean_ms * 1e-3) / 1e9, bytes=alg_bytes, finite=d["nonfinite"] == 0)
         log(f"  {st}: {mean_ms:.3f} ms/step, {res[st]['mlups']:.0f} MLUPS, {res[st]['gbps']:.0f} GB/s")
         L.close()
@@ -217,7 +217,8 @@ def main():
         "config": {
             "workload": f"supersonic Taylor-Green vortex {n}^3 (M0 1.25, Re 1600), D3Q7 14-component "
                         f"stream-collide, {head} populations, AA in-place",
-            "cells": cells, "storage": head, "block": 256, "xcd_remap": True,
+            "cells": cells, "storage": head,
+            "launch": dict(zip(("block", "tile", "grid", "xcd_remap"), r["launch"])),
         },
         "roofline": {
             "bound": "hbm",
@@ -231,6 +232,7 @@ def main():
         "variants": {st: {"ms_per_step": round(v["ms"], 4), "MLUPS": round(v["mlups"], 1),
                           "GBps": round(v["gbps"], 1), "frac_peak": round(v["gbps"] / PEAK_HBM_GBPS, 4),
                           "speedup_vs_fp32": (round(res["fp32"]["ms"] / v["ms"], 3) if "fp32" in res else None),
+                          "launch": dict(zip(("block", "tile", "grid", "xcd_remap"), v["launch"])),
                           "finite": v["finite"]}
                      for st, v in res.items()},
         "kernel_hash": kernel_hash(),

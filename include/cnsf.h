@@ -172,10 +172,15 @@ int cnsf_import_populations(cnsf_lattice* lat, const void* host, size_t bytes, i
  * measure the attainable HBM bandwidth next to the update. */
 int cnsf_hbm_copy(void* dst, const void* src, size_t bytes, void* stream);
 
-/* Kernel launch shape of the update: threads per block (64..256, multiple of
- * 64; the kernels are compiled for at most 256) and whether block indices are remapped so that each XCD works on one
- * contiguous span of cells. */
-int cnsf_set_launch(cnsf_lattice* lat, int32_t block, int32_t xcd_remap);
+/* Kernel launch shape of the update.  Each block owns a tile of `tile`
+ * consecutive cells (a multiple of `block`) and walks it `block` cells at a
+ * time; grid = 0 launches one block per tile, grid > 0 a persistent grid of
+ * that many blocks striding over the tiles; xcd_remap gives each of the 8 XCDs
+ * one contiguous span of tiles.  block: 64..256 in steps of 64 (the kernels are
+ * compiled for at most 256).  Defaults are the shapes measured fastest on
+ * MI355X for the lattice's storage type. */
+int cnsf_set_launch(cnsf_lattice* lat, int32_t block, int32_t tile, int32_t grid, int32_t xcd_remap);
+int cnsf_get_launch(const cnsf_lattice* lat, int32_t* block, int32_t* tile, int32_t* grid, int32_t* xcd_remap);
 
 const char* cnsf_last_error(void);
 const char* cnsf_status_string(int status);

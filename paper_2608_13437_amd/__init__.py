@@ -89,7 +89,8 @@ def library():
             "cnsf_export_populations": [vp, vp, sz, C.POINTER(i64), C.POINTER(i32)],
             "cnsf_import_populations": [vp, vp, sz, i64, i32],
             "cnsf_hbm_copy": [vp, vp, sz, vp],
-            "cnsf_set_launch": [vp, i32, i32],
+            "cnsf_set_launch": [vp, i32, i32, i32, i32],
+            "cnsf_get_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
             "cnsf_batch_required_bytes": [pp, i32, C.POINTER(sz)],
             "cnsf_batch_create": [pp, i32, vp, sz, vp, C.POINTER(vp)],
             "cnsf_batch_destroy": [vp],
@@ -177,8 +178,14 @@ def cnsf_hbm_copy(dst: int, src: int, nbytes: int, stream: int):
     _check(library().cnsf_hbm_copy(C.c_void_p(dst), C.c_void_p(src), nbytes, C.c_void_p(stream)))
 
 
-def cnsf_set_launch(h, block: int, xcd_remap: int):
-    _check(library().cnsf_set_launch(h, block, xcd_remap))
+def cnsf_set_launch(h, block: int, tile: int, grid: int, xcd_remap: int):
+    _check(library().cnsf_set_launch(h, block, tile, grid, xcd_remap))
+
+
+def cnsf_get_launch(h):
+    v = [C.c_int32() for _ in range(4)]
+    _check(library().cnsf_get_launch(h, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
 
 
 def cnsf_status_string(s: int) -> str:
@@ -291,8 +298,12 @@ class Lattice:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         cnsf_import_populations(self.h, buf.ctypes.data, buf.nbytes, step, parity)
 
-    def set_launch(self, block: int = 256, xcd_remap: bool = True):
-        cnsf_set_launch(self.h, block, int(bool(xcd_remap)))
+    def set_launch(self, block: int = 256, tile: int | None = None, grid: int = 0, xcd_remap: bool = True):
+        cnsf_set_launch(self.h, block, block if tile is None else tile, grid, int(bool(xcd_remap)))
+
+    def get_launch(self):
+        """(block, tile, grid, xcd_remap) of the update launch."""
+        return cnsf_get_launch(self.h)
 
 
 # ---------------------------------------------------------------- batch

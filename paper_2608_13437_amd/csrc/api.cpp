@@ -38,6 +38,23 @@ const char* last_error() { return g_err.c_str(); }
 
 size_t elem_bytes(int storage) { return storage == CNSF_STORAGE_FP32 ? 4 : 2; }
 
+// FP32: one block per 1024-cell tile; 16-bit storage: a persistent grid of 12
+// blocks per compute unit striding over 1024-cell tiles.
+Launch default_launch(int storage) {
+  Launch lc;
+  lc.block = 256;
+  lc.tile = 1024;
+  lc.grid = 0;
+  lc.remap = 1;
+  if (storage != CNSF_STORAGE_FP32) {
+    int dev = 0, ncu = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    lc.grid = 12 * ncu;
+  }
+  return lc;
+}
+
 uint64_t padded_plane(uint64_t ncells) { return (ncells + 255u) / 256u * 256u; }
 
 int validate(const cnsf_params* p) {
@@ -201,8 +218,7 @@ struct cnsf_lattice {
   int device = 0;
   int64_t step = 0;
   int parity = 0;
-  int block = 256;
-  int remap = 1;
+  Launch lc;
   int* dflag = nullptr;               // device error flag
   DiagPartial* partials = nullptr;    // diagnostics block partials
   DiagPartial* dresult = nullptr;
@@ -253,6 +269,7 @@ int cnsf_create(const cnsf_params* p, void* dev_buf, size_t bytes, void* stream,
   L->cd = derive_codec(p, L->phd);
   L->stream = (hipStream_t)stream;
   L->bytes = need;
+  L->lc = default_launch(p->storage);
   (void)hipGetDevice(&L->device);
   hipError_t e;
   if (dev_buf) {
@@ -290,11 +307,15 @@ int cnsf_destroy(cnsf_lattice* L) {
   return CNSF_OK;
 }
 
-int cnsf_set_launch(cnsf_lattice* L, int32_t block, int32_t xcd_remap) {
+int cnsf_set_launch(cnsf_lattice* L, int32_t block, int32_t tile, int32_t grid, int32_t xcd_remap) {
   if (!L) return fail(CNSF_E_INVALID, "lattice is NULL");
   if (block < 64 || block > 256 || block % 64) return fail(CNSF_E_INVALID, "block %d not a multiple of 64 in [64, 256]", block);
-  L->block = block;
-  L->remap = xcd_remap ? 1 : 0;
+  if (tile < block || tile % block) return fail(CNSF_E_INVALID, "tile %d must be a multiple of block %d", tile, block);
+  if (grid < 0) return fail(CNSF_E_INVALID, "grid %d < 0", grid);
+  L->lc.block = block;
+  L->lc.tile = tile;
+  L->lc.grid = grid;
+  L->lc.remap = xcd_remap ? 1 : 0;
   return CNSF_OK;
 }
 
@@ -336,7 +357,7 @@ int cnsf_step(cnsf_lattice* L, int64_t n) {
   if (n < 0) return fail(CNSF_E_INVALID, "n = %lld < 0", (long long)n);
   (void)hipSetDevice(L->device);
   for (int64_t s = 0; s < n; ++s) {
-    hipError_t e = launch_update(L->p.storage, L->pop, L->g, L->ph, L->cd, L->parity, L->block, L->remap, L->stream);
+    hipError_t e = launch_update(L->p.storage, L->pop, L->g, L->ph, L->cd, L->parity, L->lc, L->stream);
     if (e != hipSuccess) return hip_fail(e, "update launch");
     L->parity ^= 1;
     ++L->step;
@@ -403,6 +424,15 @@ int cnsf_diagnostics(cnsf_lattice* L, int32_t flags, cnsf_diag* d) {
   d->min_p = r.min_p;
   d->sensor_fraction = r.sensor / n;
   d->nonfinite = (int64_t)r.nonfinite;
+  return CNSF_OK;
+}
+
+int cnsf_get_launch(const cnsf_lattice* L, int32_t* block, int32_t* tile, int32_t* grid, int32_t* xcd_remap) {
+  if (!L) return fail(CNSF_E_INVALID, "lattice is NULL");
+  if (block) *block = L->lc.block;
+  if (tile) *tile = L->lc.tile;
+  if (grid) *grid = L->lc.grid;
+  if (xcd_remap) *xcd_remap = L->lc.remap;
   return CNSF_OK;
 }
 

@@ -289,7 +289,12 @@ int cnsf_batch_step(cnsf_batch* b, int64_t n, int32_t mode) {
       for (size_t j = 0; j < b->m.size() && e == hipSuccess; ++j) {
         const Member& M = b->m[j];
         void* pop = (char*)b->base + M.pop_offset * elem_bytes(b->storage);
-        e = launch_update(b->storage, pop, M.g, M.ph, M.cd, b->parity, b->block, 1, b->stream);
+        Launch lc;
+        lc.block = b->block;
+        lc.tile = (int)b->tile;
+        lc.grid = 0;
+        lc.remap = 1;
+        e = launch_update(b->storage, pop, M.g, M.ph, M.cd, b->parity, lc, b->stream);
       }
       b->parity ^= 1;
     }

@@ -7,8 +7,20 @@
 
 namespace cnsf {
 
-hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity, int block,
-                         int remap, hipStream_t s);
+// Launch shape of the update: threads per block (<= 256), cells per tile (a
+// multiple of block), blocks in a persistent grid (0: one block per tile) and
+// the XCD-contiguous tile remap.
+struct Launch {
+  int block = 256;
+  int tile = 1024;
+  int grid = 0;
+  int remap = 1;
+};
+// Shape measured best on MI355X for each storage type (512^3 Taylor-Green).
+Launch default_launch(int storage);
+
+hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
+                         const Launch& lc, hipStream_t s);
 hipError_t launch_init(int storage, void* pop, const double* Q, const Geom& g, const PhysD& ph, const Codec& cd,
                        uint32_t cell0, uint32_t nslab, int* bad, hipStream_t s);
 hipError_t launch_moments(int storage, const void* pop, double* out, const Geom& g, const Codec& cd, int parity,

@@ -11,29 +11,37 @@
 
 namespace cnsf {
 
-// Block index remap: hardware deals blocks round-robin over the 8 XCDs; this
-// gives XCD j one contiguous span of blocks so that the cache lines shared by
-// neighbouring blocks (the +-x halo of the odd pass) stay in one L2.
+// Tile index remap: hardware deals blocks round-robin over the 8 XCDs; this
+// gives XCD j one contiguous span of tiles so that the cache lines shared by
+// neighbouring tiles (the +-x halo of the odd pass) stay in one L2.
 __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
   const uint32_t per = nb / 8u, rem = nb % 8u;
   const uint32_t j = b % 8u, q = b / 8u;
   return j * per + (j < rem ? j : rem) + q;
 }
 
+// One block owns a tile of `tile` consecutive cells and walks it blockDim
+// cells at a time (so each wave streams through consecutive segments of
+// every plane); with a persistent grid (fewer blocks than tiles) the blocks
+// stride over the tiles.
 template <int ST, int BC, bool SC>
 __global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restrict__ pop, const Geom g, const Phys ph,
-                                                 const Codec cd, int parity, int remap) {
-  uint32_t bid = blockIdx.x;
-  if (remap) bid = xcd_block(bid, gridDim.x);
-  const uint32_t c = bid * blockDim.x + threadIdx.x;
-  if (c >= g.ncells) return;
-  const Nbr n = neighbours(c, g);
-  uint32_t off[NV];
-  stream_offsets<ST, BC>(g, n, parity, off);
-  float gv[NC][NV];
-  gather<ST, BC, SC, float>(pop, g, cd, n, parity, off, gv);
-  update_cell(gv, cd, ph);
-  scatter<ST, BC, SC>(pop, g, cd, n, parity, off, gv);
+                                                const Codec cd, int parity, uint32_t tile, uint32_t ntiles, int remap) {
+  for (uint32_t t0 = blockIdx.x; t0 < ntiles; t0 += gridDim.x) {
+    const uint32_t t = (remap && gridDim.x >= ntiles) ? xcd_block(t0, ntiles) : t0;
+    const uint32_t first = t * tile;
+    for (uint32_t j = threadIdx.x; j < tile; j += blockDim.x) {
+      const uint32_t c = first + j;
+      if (c >= g.ncells) break;
+      const Nbr n = neighbours(c, g);
+      uint32_t off[NV];
+      stream_offsets<ST, BC>(g, n, parity, off);
+      float gv[NC][NV];
+      gather<ST, BC, SC, float>(pop, g, cd, n, parity, off, gv);
+      update_cell(gv, cd, ph);
+      scatter<ST, BC, SC>(pop, g, cd, n, parity, off, gv);
+    }
+  }
 }
 
 // f = f^eq(Q) for cells of z-planes [z0, z0 + nzs); FP64 arithmetic.
@@ -100,19 +108,20 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
 
 // ------------------------------------------------------------------ launchers
 template <int ST, int BC, bool SC>
-static hipError_t launch_update_t(void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity, int block,
-                                  int remap, hipStream_t s) {
-  const uint32_t nb = (g.ncells + block - 1) / block;
-  hipLaunchKernelGGL((k_update<ST, BC, SC>), dim3(nb), dim3(block), 0, s, (typename Store<ST>::T*)pop, g, ph, cd,
-                     parity, remap);
+static hipError_t launch_update_t(void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
+                                  const Launch& lc, hipStream_t s) {
+  const uint32_t ntiles = (g.ncells + lc.tile - 1) / lc.tile;
+  const uint32_t nb = (lc.grid > 0 && (uint32_t)lc.grid < ntiles) ? (uint32_t)lc.grid : ntiles;
+  hipLaunchKernelGGL((k_update<ST, BC, SC>), dim3(nb), dim3(lc.block), 0, s, (typename Store<ST>::T*)pop, g, ph, cd,
+                     parity, (uint32_t)lc.tile, ntiles, lc.remap);
   return hipGetLastError();
 }
 
-hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity, int block,
-                         int remap, hipStream_t s) {
+hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
+                         const Launch& lc, hipStream_t s) {
   const bool sc = cd.scaled != 0;
 #define CNSF_CASE(ST, BC, SC) \
-  if (storage == ST && g.bc_x == BC && sc == SC) return launch_update_t<ST, BC, SC>(pop, g, ph, cd, parity, block, remap, s);
+  if (storage == ST && g.bc_x == BC && sc == SC) return launch_update_t<ST, BC, SC>(pop, g, ph, cd, parity, lc, s);
   CNSF_CASE(0, 0, false) CNSF_CASE(0, 1, false) CNSF_CASE(0, 2, false)
   CNSF_CASE(1, 0, false) CNSF_CASE(1, 1, false) CNSF_CASE(1, 2, false)
   CNSF_CASE(2, 0, false) CNSF_CASE(2, 1, false) CNSF_CASE(2, 2, false)

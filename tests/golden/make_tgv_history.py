@@ -1,0 +1,61 @@
+"""Write the FP64 oracle's Taylor-Green diagnostic history (Eq. (7)) to a golden file.
+
+Runs only the oracle and the seeded input generator: the supersonic
+Taylor-Green vortex (M0 1.25, Re 1600, Pr 0.71, mu ~ T^0.76) at N^3 from
+t_c = 0 to t_c = T_END, recording E_k, eps_s, eps_d, mass and energy every
+EVERY steps.
+
+usage: python tests/golden/make_tgv_history.py [N] [T_END] [EVERY]
+"""
+import json
+import os
+import sys
+import time
+import warnings
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+from oracle import diagnostics, lbm  # noqa: E402
+
+
+def main():
+    warnings.simplefilter("ignore", RuntimeWarning)
+    n = int(sys.argv[1]) if len(sys.argv) > 1 else 64
+    t_end = float(sys.argv[2]) if len(sys.argv) > 2 else 20.0
+    every = int(sys.argv[3]) if len(sys.argv) > 3 else 10
+    case = W.tgv(n)
+    prm = case.params
+    steps = int(np.ceil(t_end / prm["dt"] / every)) * every
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"tgv{n}_history.json")
+    hist = dict(step=[], t=[], E_k=[], eps_s=[], eps_d=[], mass=[], energy=[])
+    f = lbm.init_populations(case.Q0, prm)
+    t0 = time.time()
+    for s in range(steps + 1):
+        if s % every == 0:
+            d = diagnostics.diagnostics(lbm.moments(f), prm)
+            hist["step"].append(s)
+            hist["t"].append(s * prm["dt"])
+            for k in ("E_k", "eps_s", "eps_d", "mass", "energy"):
+                hist[k].append(d[k])
+            if not np.isfinite(d["E_k"]):
+                break
+            if s % (every * 20) == 0:
+                print(f"step {s}/{steps} t_c {s * prm['dt']:.2f} E_k {d['E_k']:.5f} eps_d {d['eps_d']:.3e} "
+                      f"({time.time() - t0:.0f} s)", flush=True)
+        if s < steps:
+            f = lbm.step(f, prm)
+    rec = dict(source="oracle.lbm FP64, oracle.diagnostics (Eq. (7), spectral derivatives)",
+               case=dict(n=n, M0=1.25, Re=1600, Pr=0.71, law="power 0.76", f_mu=prm["f_mu"], dt=prm["dt"],
+                         C_sigma=prm["C_sigma"], J_min=prm["J_min"], omega_min=prm["omega_min"]),
+               every=every, steps=steps, wall_seconds=round(time.time() - t0, 1), history=hist)
+    with open(out, "w") as fh:
+        json.dump(rec, fh)
+    print("wrote", out)
+
+
+if __name__ == "__main__":
+    main()

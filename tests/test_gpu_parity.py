@@ -43,13 +43,14 @@ def compare(Qg, Qo, prm):
     return {k: rel_l2(fg[k], fo[k]) for k in fg}
 
 
-def run_gpu(case, steps, *, storage=None, block=256, remap=True):
+def run_gpu(case, steps, *, storage=None, launch=None):
     cnsf = _cnsf()
     prm = dict(case.params)
     if storage is not None:
         prm["storage"] = storage
     L = cnsf.Lattice(prm)
-    L.set_launch(block, remap)
+    if launch is not None:
+        L.set_launch(*launch)
     L.set_state(case.Q0)
     L.step(steps)
     Q = L.moments()
@@ -126,12 +127,15 @@ def test_becker_equilibrium_ends_fp32():
     assert all(v < 1e-5 for v in err.values()), err
 
 
-@pytest.mark.parametrize("block,remap", [(64, False), (128, True), (192, True), (256, False)])
-def test_launch_shapes_bitwise_equal(block, remap):
+@pytest.mark.parametrize("storage", [W.STORAGE_FP32, W.STORAGE_FP16])
+@pytest.mark.parametrize("launch", [(64, 64, 0, False), (128, 512, 0, True), (256, 256, 0, False),
+                                    (256, 1024, 3, True), (192, 768, 2, False), (256, 2048, 0, True)])
+def test_launch_shapes_bitwise_equal(launch, storage):
+    """Tiles, persistent grids and the XCD remap only reorder independent cells."""
     case = W.random_case(13, 11, 9, seed=5, sensor=True, amp=0.5)
-    log(f"case {case.name} block {block} remap {remap}")
-    _, Qa = run_gpu(case, 7, block=256, remap=True)
-    _, Qb = run_gpu(case, 7, block=block, remap=remap)
+    log(f"case {case.name} launch {launch} storage {storage}")
+    _, Qa = run_gpu(case, 7, storage=storage)
+    _, Qb = run_gpu(case, 7, storage=storage, launch=launch)
     assert np.array_equal(Qa, Qb)
 
 
@@ -140,7 +144,7 @@ def test_launch_shape_beyond_compiled_bound_rejected():
     case = W.random_case(8, 8, 8, seed=5)
     L = cnsf.Lattice(case.params)
     with pytest.raises(cnsf.CnsfError) as e:
-        L.set_launch(512, True)
+        L.set_launch(512, 512, 0, True)
     assert e.value.status == cnsf.CNSF_E_INVALID
 
 
