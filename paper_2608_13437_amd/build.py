@@ -37,18 +37,21 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
-    os.makedirs(OBJ, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 4, defines=(), lib_path: str = LIB) -> str:
+    """Compile every source and link the library (variant builds: extra -D defines, another path)."""
+    obj_dir = OBJ if not defines else OBJ + "_" + "_".join(d.replace("=", "") for d in defines)
+    os.makedirs(obj_dir, exist_ok=True)
     cc = hipcc()
+    flags = HIPCC_FLAGS + [f"-D{d}" for d in defines]
     objs = []
     procs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         if not os.path.exists(path):
             continue
-        obj = os.path.join(OBJ, src + ".o")
+        obj = os.path.join(obj_dir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [cc] + HIPCC_FLAGS + lang + ["-c", path, "-o", obj]
+        cmd = [cc] + flags + lang + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -57,15 +60,15 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             _wait(procs.pop(0), verbose)
     for p in procs:
         _wait(p, verbose)
-    tmp = LIB + ".tmp"
+    tmp = lib_path + ".tmp"
     cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 def _wait(item, verbose):

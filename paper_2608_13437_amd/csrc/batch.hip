@@ -36,10 +36,11 @@ struct Member {
   uint32_t ntiles;
 };
 
-template <int ST, bool SC>
+template <int ST, bool SC, int PAR>
 __global__ void __launch_bounds__(256) k_batch_update(typename Store<ST>::T* __restrict__ base,
                                                       const Member* __restrict__ members, int nmembers,
-                                                      uint32_t total_tiles, uint32_t tile, int parity) {
+                                                      uint32_t total_tiles, uint32_t tile) {
+  constexpr int parity = PAR;
   for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
     // member of tile t (uniform): last m with tile0 <= t
     int lo = 0, hi = nmembers - 1;
@@ -69,11 +70,15 @@ __global__ void __launch_bounds__(256) k_batch_update(typename Store<ST>::T* __r
 static hipError_t launch_batch(int storage, bool scaled, void* base, const Member* members, int n,
                                uint32_t total_tiles, uint32_t tile, int block, int grid, int parity, hipStream_t s) {
   const uint32_t nb = grid > 0 ? (uint32_t)grid : total_tiles;
-#define CNSF_CASE(ST, SC, T)                                                                                    \
-  if (storage == ST && scaled == SC) {                                                                          \
-    hipLaunchKernelGGL((k_batch_update<ST, SC>), dim3(nb), dim3(block), 0, s, (T*)base, members, n, total_tiles, \
-                       tile, parity);                                                                           \
-    return hipGetLastError();                                                                                   \
+#define CNSF_CASE(ST, SC, T)                                                                            \
+  if (storage == ST && scaled == SC) {                                                                  \
+    if (parity)                                                                                         \
+      hipLaunchKernelGGL((k_batch_update<ST, SC, 1>), dim3(nb), dim3(block), 0, s, (T*)base, members, n, \
+                         total_tiles, tile);                                                            \
+    else                                                                                                \
+      hipLaunchKernelGGL((k_batch_update<ST, SC, 0>), dim3(nb), dim3(block), 0, s, (T*)base, members, n, \
+                         total_tiles, tile);                                                            \
+    return hipGetLastError();                                                                           \
   }
   CNSF_CASE(0, false, float)
   CNSF_CASE(1, false, uint16_t)

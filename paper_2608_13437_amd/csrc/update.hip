@@ -22,13 +22,26 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
 
 // One block owns a tile of `tile` consecutive cells and walks it blockDim
 // cells at a time (so each wave streams through consecutive segments of
-// every plane); with a persistent grid (fewer blocks than tiles) the blocks
-// stride over the tiles.
-template <int ST, int BC, bool SC>
+// every plane).  With one block per tile the remap hands XCD j a contiguous
+// span of tiles; with a persistent grid (fewer blocks than tiles, a multiple
+// of 8) the blocks of XCD j stride over the j-th eighth of the tiles, so
+// neighbouring tiles, which share the +-x halo lines of the odd pass, are in
+// flight in the same L2.  Without the remap the blocks stride over all tiles.
+template <int ST, int BC, bool SC, int PAR>
 __global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restrict__ pop, const Geom g, const Phys ph,
-                                                const Codec cd, int parity, uint32_t tile, uint32_t ntiles, int remap) {
-  for (uint32_t t0 = blockIdx.x; t0 < ntiles; t0 += gridDim.x) {
-    const uint32_t t = (remap && gridDim.x >= ntiles) ? xcd_block(t0, ntiles) : t0;
+                                                const Codec cd, uint32_t tile, uint32_t ntiles, int remap) {
+  constexpr int parity = PAR;
+  uint32_t t_begin = blockIdx.x, t_step = gridDim.x, t_end = ntiles;
+  if (remap && gridDim.x >= ntiles) {
+    t_begin = xcd_block(blockIdx.x, ntiles);
+    t_end = t_begin + 1;
+  } else if (remap && (gridDim.x & 7u) == 0) {
+    const uint32_t per = (ntiles + 7u) / 8u, x = blockIdx.x & 7u;
+    t_begin = x * per + (blockIdx.x >> 3);
+    t_step = gridDim.x >> 3;
+    t_end = min(ntiles, (x + 1u) * per);
+  }
+  for (uint32_t t = t_begin; t < t_end; t += t_step) {
     const uint32_t first = t * tile;
     for (uint32_t j = threadIdx.x; j < tile; j += blockDim.x) {
       const uint32_t c = first + j;
@@ -112,8 +125,13 @@ static hipError_t launch_update_t(void* pop, const Geom& g, const Phys& ph, cons
                                   const Launch& lc, hipStream_t s) {
   const uint32_t ntiles = (g.ncells + lc.tile - 1) / lc.tile;
   const uint32_t nb = (lc.grid > 0 && (uint32_t)lc.grid < ntiles) ? (uint32_t)lc.grid : ntiles;
-  hipLaunchKernelGGL((k_update<ST, BC, SC>), dim3(nb), dim3(lc.block), 0, s, (typename Store<ST>::T*)pop, g, ph, cd,
-                     parity, (uint32_t)lc.tile, ntiles, lc.remap);
+  using T = typename Store<ST>::T;
+  if (parity)
+    hipLaunchKernelGGL((k_update<ST, BC, SC, 1>), dim3(nb), dim3(lc.block), 0, s, (T*)pop, g, ph, cd,
+                       (uint32_t)lc.tile, ntiles, lc.remap);
+  else
+    hipLaunchKernelGGL((k_update<ST, BC, SC, 0>), dim3(nb), dim3(lc.block), 0, s, (T*)pop, g, ph, cd,
+                       (uint32_t)lc.tile, ntiles, lc.remap);
   return hipGetLastError();
 }
 

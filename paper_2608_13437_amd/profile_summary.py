@@ -1,0 +1,63 @@
+"""Summarise rocprofv3 output of the update kernel into short text files.
+
+usage:
+  python -m paper_2608_13437_amd.profile_summary stats  <kernel_stats.csv> <out.txt> "<command>"
+  python -m paper_2608_13437_amd.profile_summary traffic <fetch.csv> <write.csv> <copy_fetch.csv>
+         <copy_write.csv> <copy_bytes> <storage> <out.json> "<commands>"
+The traffic summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the
+update by the factor the same counter needs on a plain copy of known size.
+"""
+import csv
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SOURCES = ["paper_2608_13437_amd/csrc/update.hip", "paper_2608_13437_amd/csrc/cnsf_impl.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for rel in SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stats(path, out, command):
+    rows = list(csv.DictReader(open(path)))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", f"# kernel source hash: {kernel_hash()}", ""]
+    lines.append(f"{'calls':>6} {'avg_ms':>10} {'min_ms':>10} {'max_ms':>10} {'pct':>7}  kernel")
+    for r in rows:
+        lines.append(f"{int(r['Calls']):>6} {float(r['AverageNs']) / 1e6:>10.4f} {float(r['MinNs']) / 1e6:>10.4f} "
+                     f"{float(r['MaxNs']) / 1e6:>10.4f} {float(r['Percentage']):>7.2f}  {r['Name'][:110]}")
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def counter(path, name_sub):
+    return [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if name_sub in r["Kernel_Name"]]
+
+
+def traffic(fetch, write, cfetch, cwrite, copy_bytes, storage, out, command):
+    f, w = counter(fetch, "k_update"), counter(write, "k_update")
+    cf, cw = counter(cfetch, "k_copy"), counter(cwrite, "k_copy")
+    copy_bytes = int(copy_bytes)
+    ffac = sum(copy_bytes / (x * 1024) for x in cf) / len(cf)
+    wfac = sum(copy_bytes / (x * 1024) for x in cw) / len(cw)
+    fb = [x * 1024 * ffac for x in f]
+    wb = [x * 1024 * wfac for x in w]
+    per = [a + b for a, b in zip(fb, wb)]
+    rec = json.load(open(out)) if os.path.exists(out) else {}
+    rec["kernel_hash"] = kernel_hash()
+    rec["copy_factor"] = dict(FETCH_SIZE=round(ffac, 4), WRITE_SIZE=round(wfac, 4))
+    rec[storage] = dict(fetch_bytes=[round(x) for x in fb], write_bytes=[round(x) for x in wb],
+                        bytes_per_launch=round(sum(per) / len(per)), command=command)
+    json.dump(rec, open(out, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats(*sys.argv[2:5])
+    else:
+        traffic(*sys.argv[2:10])

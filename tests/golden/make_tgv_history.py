@@ -5,7 +5,7 @@ Taylor-Green vortex (M0 1.25, Re 1600, Pr 0.71, mu ~ T^0.76) at N^3 from
 t_c = 0 to t_c = T_END, recording E_k, eps_s, eps_d, mass and energy every
 EVERY steps.
 
-usage: python tests/golden/make_tgv_history.py [N] [T_END] [EVERY]
+usage: python tests/golden/make_tgv_history.py [N] [T_END] [EVERY] [F_MU]
 """
 import json
 import os
@@ -27,10 +27,12 @@ def main():
     n = int(sys.argv[1]) if len(sys.argv) > 1 else 64
     t_end = float(sys.argv[2]) if len(sys.argv) > 2 else 20.0
     every = int(sys.argv[3]) if len(sys.argv) > 3 else 10
-    case = W.tgv(n)
+    f_mu = float(sys.argv[4]) if len(sys.argv) > 4 else None
+    case = W.tgv(n, f_mu=f_mu)
     prm = case.params
     steps = int(np.ceil(t_end / prm["dt"] / every)) * every
-    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"tgv{n}_history.json")
+    tag = "" if f_mu is None else f"_fmu{f_mu:g}"
+    out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"tgv{n}{tag}_history.json")
     hist = dict(step=[], t=[], E_k=[], eps_s=[], eps_d=[], mass=[], energy=[])
     f = lbm.init_populations(case.Q0, prm)
     t0 = time.time()

@@ -442,3 +442,20 @@ def test_closed_form_wave_speed_matches_flux_jacobian(law):
         cf = float(W.char_speed(rho, un, p, prm))
         tol = 1e-10 if (un == 0.0 or law == "const") else 0.03 * num
         assert abs(num - cf) < tol
+
+
+def test_domain_of_dependence_crop_is_exact():
+    """After n steps a cell depends only on the initial cube of half-width n: a periodic
+    crop of half-width h + n reproduces the full run on its central (2h)^3 cells."""
+    N, n, h = 32, 5, 3
+    case = W.tgv(N)
+    prm = case.params
+    full = lbm.moments(lbm.run(case.Q0, prm, n))
+    zc, yc, xc = 7, 30, 16
+    H = h + n
+    idx = lambda c: np.arange(c - H, c + H) % N
+    crop = case.Q0[:, idx(zc)][:, :, idx(yc)][:, :, :, idx(xc)]
+    out = lbm.moments(lbm.run(crop, dict(prm, nx=2 * H, ny=2 * H, nz=2 * H), n))
+    a = out[:, n:n + 2 * h, n:n + 2 * h, n:n + 2 * h]
+    b = full[:, idx(zc)[n:n + 2 * h]][:, :, idx(yc)[n:n + 2 * h]][:, :, :, idx(xc)[n:n + 2 * h]]
+    assert np.array_equal(a, b)
