@@ -18,10 +18,10 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 512]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -34,15 +34,7 @@ METRIC = "MLUPS + HBM GB/s (% peak), FP32 vs FP16-storage, supersonic TGV 512^3"
 STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2}
 BYTES_PER_POP = {"fp32": 4, "fp16": 2, "bf16": 2}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_tgv512.json")
-KERNEL_SOURCES = ["paper_2608_13437_amd/csrc/update.hip", "paper_2608_13437_amd/csrc/cnsf_impl.h"]
-
-
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+from paper_2608_13437_amd.profile_summary import kernel_hash  # noqa: E402
 
 
 def log(*a):
@@ -135,7 +127,7 @@ def run_batch(cnsf, steps, warmup):
     B = cnsf.Batch([c.params for c in cases])
     for j, c in enumerate(cases):
         B.set_state(j, W.tgv_slab(c.params, 0, c.params["nz"]))
-    B.autotune(os.path.join(ROOT, "profiles", "batch_autotune.json"), steps_per_trial=10)
+    B.autotune(os.path.join(tempfile.gettempdir(), "cnsf_batch_autotune.json"), steps_per_trial=10)
     out = {}
     for name, mode in (("graph", 1), ("launch", 0), ("sequential", 2)):
         B.step(warmup, mode)
@@ -160,7 +152,7 @@ def main():
     ap.add_argument("--storage", default="all")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
-    ap.add_argument("--batch", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-only", type=int, default=0, metavar="GIB",
                     help="only run the plain copy kernel on GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -237,7 +229,7 @@ def main():
                      for st, v in res.items()},
         "kernel_hash": kernel_hash(),
     }
-    if args.batch:
+    if not args.no_batch:
         out["batch"] = run_batch(cnsf, 20, 4)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

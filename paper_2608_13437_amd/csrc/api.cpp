@@ -58,7 +58,17 @@ Launch default_launch(int storage) {
   return lc;
 }
 
-uint64_t padded_plane(uint64_t ncells) { return (ncells + 255u) / 256u * 256u; }
+// Population planes start 256-element aligned, and consecutive planes are
+// skewed by a further 256 B (64 KiB + 256 B for planes of 16 MiB and more).
+// Without the skew a power-of-two lattice puts all 98 planes of a cell at
+// the same low address bits; on MI355X the 512^3 update then runs at
+// 4.7 TB/s instead of 5.5 TB/s, depending on where the allocation lands.
+uint64_t padded_plane(uint64_t ncells, int storage) {
+  const uint64_t eb = elem_bytes(storage);
+  const uint64_t base = (ncells + 255u) / 256u * 256u;
+  const uint64_t skew = base * eb >= (16ull << 20) ? 65536 + 256 : 256;
+  return base + skew / eb;
+}
 
 int validate(const cnsf_params* p) {
   if (!p) return fail(CNSF_E_INVALID, "params is NULL");
@@ -97,7 +107,7 @@ int validate(const cnsf_params* p) {
     if (!((p->gamma - 1.0) * p->Q_ref[4] > 0.0)) return fail(CNSF_E_INVALID, "Q_ref has p <= 0");
   }
   // one component's 7 planes are addressed with 32-bit byte offsets
-  if ((uint64_t)NV * padded_plane(nc) * elem_bytes(p->storage) >= (1ull << 32) - 256)
+  if ((uint64_t)NV * padded_plane(nc, p->storage) * elem_bytes(p->storage) >= (1ull << 32) - 256)
     return fail(CNSF_E_INVALID, "%llu cells: 7 population planes exceed 4 GiB", (unsigned long long)nc);
   if (p->a_ref > 0.0 && p->a_ref * p->dt / p->dx > 0.5 * (1.0 + 1e-12))
     return fail(CNSF_E_INVALID, "a_ref dt / dx = %g exceeds the sub-characteristic bound 1/2",
@@ -191,7 +201,7 @@ Geom derive_geom(const cnsf_params* p, const PhysD& ph) {
   g.nz = p->nz;
   g.nxy = (uint32_t)p->nx * p->ny;
   g.ncells = g.nxy * (uint32_t)p->nz;
-  g.plane = padded_plane(g.ncells);
+  g.plane = padded_plane(g.ncells, p->storage);
   g.bc_x = p->bc_x;
   if (p->bc_x == CNSF_BC_DIRICHLET) {
     const Codec cd = derive_codec(p, ph);
@@ -253,7 +263,7 @@ int cnsf_required_bytes(const cnsf_params* p, size_t* bytes) {
   if (int e = validate(p)) return e;
   if (!bytes) return fail(CNSF_E_INVALID, "bytes is NULL");
   const uint64_t nc = (uint64_t)p->nx * p->ny * p->nz;
-  *bytes = (size_t)NP * padded_plane(nc) * elem_bytes(p->storage);
+  *bytes = (size_t)NP * padded_plane(nc, p->storage) * elem_bytes(p->storage);
   return CNSF_OK;
 }
 

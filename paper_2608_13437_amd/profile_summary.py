@@ -14,7 +14,8 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-SOURCES = ["paper_2608_13437_amd/csrc/update.hip", "paper_2608_13437_amd/csrc/cnsf_impl.h"]
+SOURCES = ["paper_2608_13437_amd/csrc/update.hip", "paper_2608_13437_amd/csrc/cnsf_impl.h",
+           "paper_2608_13437_amd/csrc/api.cpp"]   # api.cpp fixes the population layout
 
 
 def kernel_hash():

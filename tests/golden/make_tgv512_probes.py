@@ -1,0 +1,74 @@
+"""Write FP64 oracle values of the 512^3 Taylor-Green state after 100 steps at probe cubes.
+
+Runs only the oracle and the seeded input generator.  D3Q7 moves each
+population one face neighbour per step and the collision is cell-local, so
+after n steps a cell depends only on the initial cube of half-width n around
+it.  Each probe (edge 2*HALF) starts from a periodic-wrapped crop of edge
+2*(HALF + STEPS) of the initial field; after every step the outer layer, the
+only one the crop's own wrap reaches, is trimmed off.  The result at the probe
+is exactly the full-domain oracle's.
+
+Probe centres are drawn with numpy.random.default_rng(13437); the first three
+are fixed (one wraps the periodic x boundary).  The output file is rewritten
+after each probe, so an interrupted run keeps the probes it finished.
+
+usage: python tests/golden/make_tgv512_probes.py [NPROBES]
+"""
+import os
+import sys
+import time
+import warnings
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+from oracle import lbm  # noqa: E402
+
+N = 512
+STEPS = 100
+HALF = 4
+FIXED = [(100, 37, 500), (256, 255, 0), (411, 140, 301)]   # (z, y, x)
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tgv512_probes_100steps.npz")
+
+
+def probe_centres(n):
+    rng = np.random.default_rng(13437)
+    extra = [tuple(int(v) for v in rng.integers(0, N, size=3)) for _ in range(max(0, n - len(FIXED)))]
+    return (FIXED + extra)[:n]
+
+
+def crop_initial(prm, zc, yc, xc, H):
+    idx = lambda c: np.arange(c - H, c + H) % N
+    planes = [W.tgv_slab(prm, int(z), int(z) + 1)[:, 0] for z in idx(zc)]
+    Q = np.stack(planes, axis=1)                      # (14, 2H, N, N)
+    return np.ascontiguousarray(Q[:, :, idx(yc)][:, :, :, idx(xc)])
+
+
+def probe(prm, centre):
+    H = HALF + STEPS
+    f = lbm.init_populations(crop_initial(prm, *centre, H), prm)
+    for _ in range(STEPS):
+        f = np.ascontiguousarray(lbm.step(f, prm)[:, :, 1:-1, 1:-1, 1:-1])
+    assert f.shape[2:] == (2 * HALF,) * 3
+    return lbm.moments(f)
+
+
+def main():
+    warnings.simplefilter("ignore", RuntimeWarning)
+    nprobes = int(sys.argv[1]) if len(sys.argv) > 1 else 8
+    prm = W.tgv_params(N, storage=W.STORAGE_FP32)
+    centres, values = [], []
+    t0 = time.time()
+    for c in probe_centres(nprobes):
+        values.append(probe(prm, c))
+        centres.append(c)
+        np.savez(OUT, centres=np.array(centres, dtype=np.int64), Q=np.array(values), steps=STEPS, half=HALF,
+                 dt=prm["dt"])
+        print(f"probe {c} done ({time.time() - t0:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -312,7 +312,8 @@ def test_codec_rounds_to_nearest_even(storage):
     L.set_state(case.Q0)
     raw, step, parity = L.export_populations()
     ncells = 13 * 11 * 9
-    plane = (ncells + 255) // 256 * 256
+    plane = (ncells + 255) // 256 * 256 + 256 // 2     # 16-bit planes, 256 B skew
+    assert raw.size == 98 * plane * 2
     got = raw.view(np.uint16).reshape(98, plane)[:, :ncells]
     feq = lbm.equilibrium(case.Q0, lbm.flux(case.Q0, prm), prm).reshape(98, ncells).astype(np.float32)
     if storage == W.STORAGE_FP16:
