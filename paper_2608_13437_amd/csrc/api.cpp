@@ -58,14 +58,13 @@ Launch default_launch(int storage) {
   return lc;
 }
 
-// Population planes start 256-element aligned, and consecutive planes are
-// skewed by a further 256 B (64 KiB + 256 B for planes of 16 MiB and more).
-// Without the skew a power-of-two lattice puts all 98 planes of a cell at
-// the same low address bits; on MI355X the 512^3 update then runs at
-// 4.7 TB/s instead of 5.5 TB/s, depending on where the allocation lands.
-uint64_t padded_plane(uint64_t ncells, int storage) {
+// Elements between consecutive component regions: 7 slots of the cell count
+// rounded up to whole slot groups, plus a skew of 256 B (64 KiB + 256 B for
+// regions of 16 MiB and more) so that the regions of a power-of-two lattice
+// do not all start at the same low address bits.
+uint64_t component_stride(uint64_t ncells, int storage) {
   const uint64_t eb = elem_bytes(storage);
-  const uint64_t base = (ncells + 255u) / 256u * 256u;
+  const uint64_t base = (uint64_t)NV * ((ncells + SLOT_GROUP - 1) / SLOT_GROUP * SLOT_GROUP);
   const uint64_t skew = base * eb >= (16ull << 20) ? 65536 + 256 : 256;
   return base + skew / eb;
 }
@@ -106,9 +105,9 @@ int validate(const cnsf_params* p) {
         return fail(CNSF_E_INVALID, "Q_ref must be a gas at rest: Q_ref[%d] = %g", k, p->Q_ref[k]);
     if (!((p->gamma - 1.0) * p->Q_ref[4] > 0.0)) return fail(CNSF_E_INVALID, "Q_ref has p <= 0");
   }
-  // one component's 7 planes are addressed with 32-bit byte offsets
-  if ((uint64_t)NV * padded_plane(nc, p->storage) * elem_bytes(p->storage) >= (1ull << 32) - 256)
-    return fail(CNSF_E_INVALID, "%llu cells: 7 population planes exceed 4 GiB", (unsigned long long)nc);
+  // one component's region is addressed with 32-bit byte offsets
+  if (component_stride(nc, p->storage) * elem_bytes(p->storage) >= (1ull << 32) - 256)
+    return fail(CNSF_E_INVALID, "%llu cells: one component's 7 population slots exceed 4 GiB", (unsigned long long)nc);
   if (p->a_ref > 0.0 && p->a_ref * p->dt / p->dx > 0.5 * (1.0 + 1e-12))
     return fail(CNSF_E_INVALID, "a_ref dt / dx = %g exceeds the sub-characteristic bound 1/2",
                 p->a_ref * p->dt / p->dx);
@@ -201,7 +200,7 @@ Geom derive_geom(const cnsf_params* p, const PhysD& ph) {
   g.nz = p->nz;
   g.nxy = (uint32_t)p->nx * p->ny;
   g.ncells = g.nxy * (uint32_t)p->nz;
-  g.plane = padded_plane(g.ncells, p->storage);
+  g.cstride = component_stride(g.ncells, p->storage);
   g.bc_x = p->bc_x;
   if (p->bc_x == CNSF_BC_DIRICHLET) {
     const Codec cd = derive_codec(p, ph);
@@ -263,7 +262,7 @@ int cnsf_required_bytes(const cnsf_params* p, size_t* bytes) {
   if (int e = validate(p)) return e;
   if (!bytes) return fail(CNSF_E_INVALID, "bytes is NULL");
   const uint64_t nc = (uint64_t)p->nx * p->ny * p->nz;
-  *bytes = (size_t)NP * padded_plane(nc, p->storage) * elem_bytes(p->storage);
+  *bytes = (size_t)NC * component_stride(nc, p->storage) * elem_bytes(p->storage);
   return CNSF_OK;
 }
 

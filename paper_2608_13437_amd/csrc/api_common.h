@@ -12,7 +12,7 @@ int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* what);
 const char* last_error();
 size_t elem_bytes(int storage);
-uint64_t padded_plane(uint64_t ncells, int storage);
+uint64_t component_stride(uint64_t ncells, int storage);
 int validate(const cnsf_params* p);
 PhysD derive_phys_d(const cnsf_params* p);
 Phys to_float(const PhysD& d);

@@ -27,11 +27,20 @@ constexpr int NC = 14;   // components
 constexpr int NV = 7;    // D3Q7 velocities: 0, +x, -x, +y, -y, +z, -z
 constexpr int NP = 98;   // populations per cell
 
+// Population layout: component k owns one region of `cstride` elements.  The
+// region is cut into groups of SLOT_GROUP consecutive cells; a group holds
+// the 7 slots one after the other, SLOT_GROUP elements each, cells in linear
+// order (x fastest).  A wavefront of 64 consecutive cells therefore reads 64
+// consecutive elements of each slot, and a block's tile reads 7 contiguous
+// runs per component instead of 98 widely separated streams.
+constexpr uint32_t SLOT_GROUP_LOG2 = 10;
+constexpr uint32_t SLOT_GROUP = 1u << SLOT_GROUP_LOG2;
+
 // Lattice geometry and boundary data (kernel argument).
 struct Geom {
   uint32_t nx, ny, nz, nxy, ncells;
   uint32_t pad_;
-  uint64_t plane;          // elements between consecutive population planes
+  uint64_t cstride;        // elements between the regions of consecutive components
   int32_t bc_x;            // 0 periodic, 1 wall, 2 equilibrium ends
   float dev_left[NC];      // f^eq_{k,+x}(Q_left) - f^eq_{k,+x}(Q_ref): enters at x = 0
   float dev_right[NC];     // f^eq_{k,-x}(Q_right) - f^eq_{k,-x}(Q_ref): enters at x = nx-1
@@ -369,23 +378,27 @@ __device__ inline uint32_t odd_src(const Nbr& n, int i) {  // x - c_i
   }
 }
 
-// Byte offset, inside one component's 7 planes, of slot `slot` of cell `idx`.
-// The 7 planes of a component span less than 4 GiB (checked on the host).
-template <int ST>
-__device__ inline uint32_t slot_offset(const Geom& g, int slot, uint32_t idx) {
-  return (uint32_t)((slot * (uint32_t)g.plane + idx) * (uint32_t)sizeof(typename Store<ST>::T));
+// Element index, inside one component's region, of slot `slot` of cell `idx`.
+__host__ __device__ inline uint32_t slot_index(int slot, uint32_t idx) {
+  return (idx >> SLOT_GROUP_LOG2) * (uint32_t)(NV * SLOT_GROUP) + (uint32_t)slot * SLOT_GROUP + (idx & (SLOT_GROUP - 1u));
 }
 
-// Raw buffer access to one component's 7 planes: a 128-bit resource (base,
+// Byte offset of the same element.  A component's region spans less than
+// 4 GiB (checked on the host).
+template <int ST>
+__device__ inline uint32_t slot_offset(const Geom&, int slot, uint32_t idx) {
+  return slot_index(slot, idx) * (uint32_t)sizeof(typename Store<ST>::T);
+}
+
+// Raw buffer access to one component's region: a 128-bit resource (base,
 // byte size) in scalar registers plus one 32-bit offset per direction.  The
 // hardware drops accesses at or past the size (reads return 0).
 constexpr int BUF_WORD3 = 0x00020000;   // gfx9-family resource word 3
 
 template <int ST>
 __device__ inline __amdgpu_buffer_rsrc_t component_rsrc(const typename Store<ST>::T* pop, const Geom& g, int k) {
-  const uint64_t cstride = (uint64_t)NV * g.plane;
-  const uint32_t bytes = (uint32_t)(cstride * sizeof(typename Store<ST>::T));
-  return __builtin_amdgcn_make_buffer_rsrc((void*)(pop + (uint64_t)k * cstride), (short)0, (int)bytes, BUF_WORD3);
+  const uint32_t bytes = (uint32_t)(g.cstride * sizeof(typename Store<ST>::T));
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(pop + (uint64_t)k * g.cstride), (short)0, (int)bytes, BUF_WORD3);
 }
 
 template <int ST>
@@ -413,7 +426,7 @@ __device__ inline bool crossed_end(const Geom& g, const Nbr& n, int parity, int 
   return BC != 0 && parity && ((i == 1 && n.x == 0) || (i == 2 && n.x == g.nx - 1));
 }
 
-// The 7 byte offsets (within one component's planes) from which the current
+// The 7 byte offsets (within one component's region) from which the current
 // time level's f_i is read.  Even passes: slot i of the cell.  Odd passes:
 // slot opp(i) of x - c_i, or, for a link that crossed an x-end, slot i of the
 // cell itself (where the previous even pass left the post-collision value of

@@ -1,9 +1,9 @@
 // Fused stream-and-collide update, state initialisation and moment readout.
 //
-// One thread owns one cell.  Populations live in 98 planes (component k,
-// slot i) of `plane` elements each, x fastest inside a plane, so a wavefront
-// of 64 consecutive cells reads 64 consecutive elements of every plane.  The
-// in-place AA pattern alternates an even pass (read and write the cell's own
+// One thread owns one cell.  Populations live in 14 component regions, each
+// cut into groups of 1024 consecutive cells that hold the 7 slots back to
+// back (x fastest inside a slot), so a wavefront of 64 consecutive cells
+// reads 64 consecutive elements of every slot.  The in-place AA pattern alternates an even pass (read and write the cell's own
 // slots) and an odd pass (read from and write to the six face neighbours), so
 // one array holds the whole lattice.
 #include "cnsf_impl.h"
@@ -22,7 +22,7 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
 
 // One block owns a tile of `tile` consecutive cells and walks it blockDim
 // cells at a time (so each wave streams through consecutive segments of
-// every plane).  With one block per tile the remap hands XCD j a contiguous
+// every slot).  With one block per tile the remap hands XCD j a contiguous
 // span of tiles; with a persistent grid (fewer blocks than tiles, a multiple
 // of 8) the blocks of XCD j stride over the j-th eighth of the tiles, so
 // neighbouring tiles, which share the +-x halo lines of the odd pass, are in
@@ -75,13 +75,12 @@ __global__ void k_init(typename Store<ST>::T* __restrict__ pop, const double* __
   if (!ok) atomicOr(bad, 1);
   double feq[NC][NV];
   equilibrium_all<double>(q, P, ph.four_over_lam, feq);
-  const uint64_t cstride = (uint64_t)NV * g.plane;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    typename S::T* base = pop + (uint64_t)i * g.plane + c;
+    typename S::T* base = pop + slot_index(i, c);
 #pragma unroll
     for (int k = 0; k < NC; ++k)
-      base[k * cstride] = S::enc((float)((feq[k][i] - feq_ref<double>(cd, k, i)) * (double)cd.inv_scale[k]));
+      base[k * g.cstride] = S::enc((float)((feq[k][i] - feq_ref<double>(cd, k, i)) * (double)cd.inv_scale[k]));
   }
 }
 

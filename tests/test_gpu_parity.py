@@ -312,9 +312,14 @@ def test_codec_rounds_to_nearest_even(storage):
     L.set_state(case.Q0)
     raw, step, parity = L.export_populations()
     ncells = 13 * 11 * 9
-    plane = (ncells + 255) // 256 * 256 + 256 // 2     # 16-bit planes, 256 B skew
-    assert raw.size == 98 * plane * 2
-    got = raw.view(np.uint16).reshape(98, plane)[:, :ncells]
+    # 14 component regions; cells in groups of 1024 holding the 7 slots back
+    # to back; region stride 7 * 2048 elements + 256 B of skew
+    cstride = 7 * 2048 + 256 // 2
+    assert raw.size == 14 * cstride * 2
+    regions = raw.view(np.uint16).reshape(14, cstride)
+    c = np.arange(ncells)
+    idx = (c[None, :] >> 10) * 7 * 1024 + np.arange(7)[:, None] * 1024 + (c[None, :] & 1023)   # (7, ncells)
+    got = regions[:, idx].reshape(98, ncells)
     feq = lbm.equilibrium(case.Q0, lbm.flux(case.Q0, prm), prm).reshape(98, ncells).astype(np.float32)
     if storage == W.STORAGE_FP16:
         want = feq.astype(np.float16).view(np.uint16)
