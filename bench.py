@@ -70,6 +70,21 @@ def time_update(L, steps, warmup):
     return float(np.mean(per)), float(np.min(per)), wall
 
 
+def second_allocation_ms(cnsf, L, prm, steps, warmup):
+    """The same state in a second, coexisting population array: HBM throughput of
+    this access pattern depends on where the driver places the array (the
+    allocations' speeds differ by up to 20% on MI355X), so the spread is shown
+    beside the headline figure."""
+    import torch
+    L2 = cnsf.Lattice(prm)
+    L2.buf.copy_(L.buf)
+    torch.cuda.synchronize()
+    ms = time_update(L2, steps, warmup)[0]
+    L2.close()
+    del L2
+    return ms
+
+
 def copy_bandwidth(cnsf, nbytes=8 << 30, reps=10):
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -90,7 +105,7 @@ def copy_bandwidth(cnsf, nbytes=8 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(n=64, steps=12):
+def cpu_baseline(n=64, steps=48):
     """The FP64 oracle (NumPy, single-threaded elementwise code) on a bounded sample."""
     import warnings
     warnings.simplefilter("ignore", RuntimeWarning)
@@ -153,6 +168,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-placement", action="store_true", help="skip the second-allocation timing")
     ap.add_argument("--copy-only", type=int, default=0, metavar="GIB",
                     help="only run the plain copy kernel on GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -173,13 +189,19 @@ def main():
         return
 
     storages = list(STORAGES) if args.storage == "all" else [args.storage]
+    head = "fp32" if "fp32" in storages else storages[0]
+    placement = None
     n = args.n
     cells = n ** 3
     res = {}
     for st in storages:
         L, prm = load_lattice_tgv(cnsf, n, st)
         launch = L.get_launch()
+        if st == head and not args.no_placement:
+            placement = [None, second_allocation_ms(cnsf, L, prm, args.steps, args.warmup)]
         mean_ms, min_ms, wall = time_update(L, args.steps, args.warmup)
+        if st == head and not args.no_placement:
+            placement[0] = mean_ms
         d = L.diagnostics(spectral=False)
         alg_bytes = 98 * 2 * BYTES_PER_POP[st] * cells
         res[st] = dict(ms=mean_ms, min_ms=min_ms, wall=wall, mlups=cells / (mean_ms * 1e-3) / 1e6, launch=launch,
@@ -189,7 +211,6 @@ def main():
         del L
         torch.cuda.empty_cache()
 
-    head = "fp32" if "fp32" in res else storages[0]
     r = res[head]
     copy_gbps = None if args.no_copy else round(copy_bandwidth(cnsf), 1)
     traffic = traffic_entry(head, r["ms"])
@@ -229,6 +250,9 @@ def main():
                      for st, v in res.items()},
         "kernel_hash": kernel_hash(),
     }
+    if placement is not None:
+        out["placement"] = {"storage": head, "ms_per_step": [round(x, 4) for x in placement],
+                            "note": "same state in two coexisting allocations; value is the first"}
     if not args.no_batch:
         out["batch"] = run_batch(cnsf, 20, 4)
     if not args.no_cpu:

@@ -1,7 +1,7 @@
 """Summarise rocprofv3 output of the update kernel into short text files.
 
 usage:
-  python -m paper_2608_13437_amd.profile_summary stats  <kernel_stats.csv> <out.txt> "<command>"
+  python -m paper_2608_13437_amd.profile_summary stats  <kernel_stats.csv> <out.txt> "<command>" [bench.log]
   python -m paper_2608_13437_amd.profile_summary traffic <fetch.csv> <write.csv> <copy_fetch.csv>
          <copy_write.csv> <copy_bytes> <storage> <out.json> "<commands>"
 The traffic summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the
@@ -26,9 +26,17 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def stats(path, out, command):
+def stats(path, out, command, bench_log=None):
     rows = list(csv.DictReader(open(path)))
-    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", f"# kernel source hash: {kernel_hash()}", ""]
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", f"# kernel source hash: {kernel_hash()}"]
+    if bench_log:
+        # the JSON line bench.py printed in the profiled process itself
+        for line in open(bench_log):
+            if line.startswith("{") and '"metric"' in line:
+                rec = json.loads(line)
+                lines.append(f"# bench.py in the same process: ms_per_step {rec['ms_per_step']} "
+                             f"(mean of the even and odd launches), {rec['value']} {rec['unit']}")
+    lines.append("")
     lines.append(f"{'calls':>6} {'avg_ms':>10} {'min_ms':>10} {'max_ms':>10} {'pct':>7}  kernel")
     for r in rows:
         lines.append(f"{int(r['Calls']):>6} {float(r['AverageNs']) / 1e6:>10.4f} {float(r['MinNs']) / 1e6:>10.4f} "
@@ -59,6 +67,6 @@ def traffic(fetch, write, cfetch, cwrite, copy_bytes, storage, out, command):
 
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
-        stats(*sys.argv[2:5])
+        stats(*sys.argv[2:6])
     else:
         traffic(*sys.argv[2:10])
