@@ -42,17 +42,16 @@ size_t elem_bytes(int storage) { return storage == CNSF_STORAGE_FP32 ? 4 : 2; }
 // persistent grid of 24 blocks per compute unit striding over 2048-cell tiles
 // (measured fastest on MI355X at 512^3).
 Launch default_launch(int storage) {
+  // Measured on the 512^3 update with the grouped slot layout: one block per
+  // tile throughout; 256-cell tiles dealt to the XCDs in contiguous spans for
+  // FP32 and BF16, 512-cell tiles in hardware order for FP16.
   Launch lc;
   lc.block = 256;
-  lc.tile = 1024;
+  lc.tile = 256;
   lc.grid = 0;
   lc.remap = 1;
-  if (storage != CNSF_STORAGE_FP32) {
-    int dev = 0, ncu = 256;
-    (void)hipGetDevice(&dev);
-    (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    lc.tile = 2048;
-    lc.grid = 24 * ncu;
+  if (storage == CNSF_STORAGE_FP16) {
+    lc.tile = 512;
     lc.remap = 0;
   }
   return lc;

@@ -127,7 +127,7 @@ def test_becker_equilibrium_ends_fp32():
     assert all(v < 1e-5 for v in err.values()), err
 
 
-@pytest.mark.parametrize("storage", [W.STORAGE_FP32, W.STORAGE_FP16])
+@pytest.mark.parametrize("storage", [W.STORAGE_FP32, W.STORAGE_FP16, W.STORAGE_BF16])
 @pytest.mark.parametrize("launch", [(64, 64, 0, False), (128, 512, 0, True), (256, 256, 0, False),
                                     (256, 1024, 3, True), (192, 768, 2, False), (256, 2048, 0, True)])
 def test_launch_shapes_bitwise_equal(launch, storage):
