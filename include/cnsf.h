@@ -126,7 +126,7 @@ int cnsf_params_default(cnsf_params* p);
 /* Device bytes of the population array for p: 14 component regions, each
  * holding the 7 slots of every cell (cells in groups of 1024, the 7 slots of a
  * group back to back), 4 bytes (FP32) or 2 bytes (FP16 / BF16) per population,
- * with the cell count rounded up to whole groups and a small per-region skew.
+ * with the cell count rounded up to whole groups.
  * The array is the only large allocation; the in-place (AA) streaming needs
  * no second copy. */
 int cnsf_required_bytes(const cnsf_params* p, size_t* bytes);

@@ -58,14 +58,10 @@ Launch default_launch(int storage) {
 }
 
 // Elements between consecutive component regions: 7 slots of the cell count
-// rounded up to whole slot groups, plus a skew of 256 B (64 KiB + 256 B for
-// regions of 16 MiB and more) so that the regions of a power-of-two lattice
-// do not all start at the same low address bits.
+// rounded up to whole slot groups.
 uint64_t component_stride(uint64_t ncells, int storage) {
-  const uint64_t eb = elem_bytes(storage);
-  const uint64_t base = (uint64_t)NV * ((ncells + SLOT_GROUP - 1) / SLOT_GROUP * SLOT_GROUP);
-  const uint64_t skew = base * eb >= (16ull << 20) ? 65536 + 256 : 256;
-  return base + skew / eb;
+  (void)storage;
+  return (uint64_t)NV * ((ncells + SLOT_GROUP - 1) / SLOT_GROUP * SLOT_GROUP);
 }
 
 int validate(const cnsf_params* p) {

@@ -3,9 +3,10 @@
 // One thread owns one cell.  Populations live in 14 component regions, each
 // cut into groups of 1024 consecutive cells that hold the 7 slots back to
 // back (x fastest inside a slot), so a wavefront of 64 consecutive cells
-// reads 64 consecutive elements of every slot.  The in-place AA pattern alternates an even pass (read and write the cell's own
-// slots) and an odd pass (read from and write to the six face neighbours), so
-// one array holds the whole lattice.
+// reads 64 consecutive elements of every slot.  The in-place AA pattern
+// alternates an even pass (read and write the cell's own slots) and an odd
+// pass (read from and write to the six face neighbours), so one array holds
+// the whole lattice.
 #include "cnsf_impl.h"
 #include "launch.h"
 

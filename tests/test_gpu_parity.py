@@ -313,8 +313,8 @@ def test_codec_rounds_to_nearest_even(storage):
     raw, step, parity = L.export_populations()
     ncells = 13 * 11 * 9
     # 14 component regions; cells in groups of 1024 holding the 7 slots back
-    # to back; region stride 7 * 2048 elements + 256 B of skew
-    cstride = 7 * 2048 + 256 // 2
+    # to back; region stride 7 * 2048 elements
+    cstride = 7 * 2048
     assert raw.size == 14 * cstride * 2
     regions = raw.view(np.uint16).reshape(14, cstride)
     c = np.arange(ncells)

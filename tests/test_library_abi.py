@@ -59,14 +59,13 @@ def test_params_default_and_bytes(cnsf):
     p = cnsf.cnsf_params_default()
     assert p.size == ctypes.sizeof(cnsf.cnsf_params)
     # 14 component regions of 7 slots of the cell count rounded up to groups
-    # of 1024 cells, each skewed by 64 KiB + 256 B (regions of 16 MiB and
-    # more) or 256 B
+    # of 1024 cells
     q = cnsf.make_params(W.tgv_params(512))
-    assert cnsf.cnsf_required_bytes(q) == 14 * (7 * 512 ** 3 * 4 + 65536 + 256)
+    assert cnsf.cnsf_required_bytes(q) == 98 * 512 ** 3 * 4
     q.storage = W.STORAGE_FP16
-    assert cnsf.cnsf_required_bytes(q) == 14 * (7 * 512 ** 3 * 2 + 65536 + 256)
+    assert cnsf.cnsf_required_bytes(q) == 98 * 512 ** 3 * 2
     q = cnsf.make_params(W.random_params(13, 11, 9))
-    assert cnsf.cnsf_required_bytes(q) == 14 * (7 * 2048 * 4 + 256)
+    assert cnsf.cnsf_required_bytes(q) == 14 * 7 * 2048 * 4
 
 
 @pytest.mark.parametrize("field,value", [
