@@ -115,12 +115,13 @@ def test_sod_walls_fp32(n):
     assert all(v < 1e-5 for v in err.values()), err
 
 
-def test_becker_equilibrium_ends_fp32():
-    case = W.becker(128, 4, 4)
+@pytest.mark.parametrize("N", [128, 256, 512, 1024])
+def test_becker_equilibrium_ends_fp32(N):
+    case = W.becker(N, 4, 4)
     n = 400
-    log(f"case becker128x4x4 steps {n}")
+    log(f"case becker{N}x4x4 steps {n}")
     _, Qg = run_gpu(case, n)
-    c1 = W.becker(128, 1, 1)
+    c1 = W.becker(N, 1, 1)
     Qo = np.broadcast_to(run_oracle(c1, n), Qg.shape)
     err = compare(Qg, Qo, case.params)
     log(f"  rel L2 {err}")
@@ -284,6 +285,34 @@ def test_batch_matches_single_lattices():
                 log(f"  member {j}: max |batch - single| = {diff:.3e}")
                 assert np.array_equal(Qb, ref[j]), (mode, j, diff)
             B.close()
+
+
+def test_full_ensemble_matches_single_lattices_and_oracle():
+    """The 64-member Taylor-Green ensemble of the benchmark (FP16, graph replay):
+    every member bitwise equal to its own single-lattice run, the two smallest
+    members within the FP16 bound of the oracle."""
+    cnsf = _cnsf()
+    cases = W.batch_ensemble(materialize=False)
+    n = 20
+    log(f"case batch ensemble of {len(cases)} members, {n} steps")
+    B = cnsf.Batch([c.params for c in cases])
+    fields = [W.tgv_slab(c.params, 0, c.params["nz"]) for c in cases]
+    for j, Q in enumerate(fields):
+        B.set_state(j, Q)
+    B.step(n, 1)
+    for j, (c, Q) in enumerate(zip(cases, fields)):
+        L = cnsf.Lattice(c.params)
+        L.set_state(Q)
+        L.step(n)
+        assert np.array_equal(B.moments(j), L.moments()), f"member {j} ({c.name})"
+        L.close()
+    small = sorted(range(len(cases)), key=lambda j: cases[j].params["nx"])[:2]
+    for j in small:
+        Qo = lbm.moments(lbm.run(fields[j], cases[j].params, n))
+        err = compare(B.moments(j), Qo, cases[j].params)
+        log(f"  member {j} ({cases[j].name}) vs oracle: rel L2 {err}")
+        assert all(v < 2e-3 for v in err.values()), err
+    B.close()
 
 
 def test_batch_autotune_restores_state(tmp_path):
