@@ -56,7 +56,10 @@ enum cnsf_where { CNSF_HOST = 0, CNSF_DEVICE = 1 };
  * Parameters of one lattice (Table "Parameters" of Section 2.3 and the
  * declaration listing of Section 2.1).  Physical units throughout.
  *  size            sizeof(cnsf_params); set by cnsf_params_default.
- *  nx, ny, nz      lattice cells (>= 1 each; nx*ny*nz < 2^31).
+ *  nx, ny, nz      lattice cells (>= 1 each).  One component's 7 population
+ *                  slots are addressed with 32-bit byte offsets, so
+ *                  nx*ny*nz <= 153,391,104 for FP32 (535^3) and
+ *                  <= 306,783,232 for FP16 / BF16 (674^3).
  *  dx, dt          cell size and time step (> 0); lambda = dx/dt.
  *  gamma           adiabatic index (> 1).
  *  mu0, T_ref      reference viscosity (>= 0) and temperature (> 0).
@@ -149,12 +152,14 @@ int cnsf_destroy(cnsf_lattice* lat);
  * p <= 0 or a non-finite value (checked on the device). */
 int cnsf_set_state(cnsf_lattice* lat, const double* Q, int32_t z0, int32_t nzs, int32_t where);
 
-/* Enqueue n fused stream-and-collide updates (alternating even/odd in-place
- * passes).  Asynchronous. */
+/* Enqueue n fused stream-and-collide updates (Section 2.2, with the sensor of
+ * Section 2.3; alternating even/odd in-place passes).  Asynchronous; n >= 0.
+ * CNSF_E_DEVICE if a launch fails. */
 int cnsf_step(cnsf_lattice* lat, int64_t n);
 
-/* Q_k = sum_i f_{k,i} of the current time level for z-planes [z0, z0+nzs),
- * written FP64 to out (host or device) as [14][nzs][ny][nx]. */
+/* Q_k = sum_i f_{k,i} (the zeroth moment, Section 2.2) of the current time
+ * level for z-planes [z0, z0+nzs), written FP64 to out (host or device) as
+ * [14][nzs][ny][nx].  CNSF_E_SIZE if the slab leaves the lattice. */
 int cnsf_get_moments(cnsf_lattice* lat, double* out, int32_t z0, int32_t nzs, int32_t where);
 
 /* FP64 diagnostics of the current time level; flags: CNSF_DIAG_SUMS or
@@ -209,11 +214,11 @@ int cnsf_batch_set_state(cnsf_batch* b, int32_t j, const double* Q, int32_t wher
  * `graph_steps` steps (captured on first use); mode 2: one launch per member
  * per step (the sequential baseline). */
 int cnsf_batch_step(cnsf_batch* b, int64_t n, int32_t mode);
+/* Member j's moments (as cnsf_get_moments, whole lattice). */
 int cnsf_batch_get_moments(cnsf_batch* b, int32_t j, double* out, int32_t where);
 /* Launch shape of the batched kernel: threads per block (64..256, multiple of
- * 64), cells per tile
- * (multiple of block), persistent grid size in blocks (0: one block per
- * tile), and the number of steps captured per graph. */
+ * 64), cells per tile (multiple of block), persistent grid size in blocks
+ * (0: one block per tile), and the number of steps captured per graph. */
 int cnsf_batch_set_launch(cnsf_batch* b, int32_t block, int32_t tile, int32_t grid, int32_t graph_steps);
 /* Time candidate launch shapes with HIP events and keep the fastest; results
  * are cached in the JSON file `cache_path` (may be NULL) keyed by the batch's

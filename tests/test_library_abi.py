@@ -103,6 +103,27 @@ def test_lattice_too_large_for_32bit_offsets(cnsf):
         cnsf.cnsf_required_bytes(cnsf.make_params(prm))
 
 
+@pytest.mark.parametrize("storage,elem,cube,last", [(W.STORAGE_FP32, 4, 535, 153_391_104),
+                                                     (W.STORAGE_FP16, 2, 674, 306_783_232),
+                                                     (W.STORAGE_BF16, 2, 674, 306_783_232)])
+def test_largest_accepted_lattice(cnsf, storage, elem, cube, last):
+    """A component's 7 slots (cells rounded up to groups of 1024) stay below
+    2^32 - 256 bytes: the documented limits are exact."""
+    assert 7 * last * elem < 2 ** 32 - 256 <= 7 * (last + 1024) * elem and last % 1024 == 0
+
+    def bytes_for(nx, ny, nz):
+        prm = dict(W.default_params(nx, ny, nz), storage=storage)
+        return cnsf.cnsf_required_bytes(cnsf.make_params(prm))
+
+    assert bytes_for(last, 1, 1) == 98 * last * elem
+    with pytest.raises(cnsf.CnsfError) as e:
+        bytes_for(last + 1, 1, 1)
+    assert e.value.status == cnsf.CNSF_E_INVALID
+    assert bytes_for(cube, cube, cube) == 14 * 7 * ((cube ** 3 + 1023) // 1024 * 1024) * elem
+    with pytest.raises(cnsf.CnsfError):
+        bytes_for(cube + 1, cube + 1, cube + 1)
+
+
 def test_status_strings(cnsf):
     assert cnsf.cnsf_status_string(0) == "ok"
     assert "HIP" in cnsf.cnsf_status_string(3)
