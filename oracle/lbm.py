@@ -31,6 +31,25 @@ Readings where the paper is silent (each listed in the design notes):
 * The source enters as w_i dt S_k with no half-step correction.
 * One omega_h relaxes all 98 populations of a cell.
 
+Pins (tests/test_oracle_pins.py; each checks against something other than
+this code, so no function here is left with parity unpinned):
+* equilibrium: its zeroth, first and second moments give Q, Phi and c_s^2 Q
+  (closed forms of the lattice), and D3Q7's weights are isotropic.
+* flux, viscosity, kappa: the characteristic speeds of the flux Jacobian
+  equal the closed-form roots of the linearised system for constant,
+  power-law and Sutherland viscosity; the Euler part converges to the exact
+  Sod solution (star state equal to the textbook values), and the viscous and
+  heat-flux parts to the closed-form Becker shock; Lambda's divergence is the
+  deviatoric strain rate.
+* source, collide: conservation to round-off and the exact decay of the
+  summed stress and heat flux by (1 - dt/tau) per step.
+* tau_base: a passive entropy mode diffuses at c_s^2 (tau_b - 1/2) dx^2/dt,
+  and the added viscosity is f_mu mu/rho.
+* dilatation, relaxation_rate: the estimate equals dt times the spectral
+  divergence of a prescribed field; with C_sigma = 0 the rate is plain BGK.
+* stream: brute force on 4^3 grids, fixed points, symmetry, the wall equal
+  to the mirror-doubled periodic domain, y/z-uniform data equal to 1D.
+
 Array layout: f has shape (14, 7, nz, ny, nx); Q has shape (14, nz, ny, nx).
 """
 from __future__ import annotations
