@@ -10,6 +10,14 @@ spectrally on the periodic box and mu_local applied per cell.
 Readings: E_k = <rho |u|^2 / 2> / rho_ref (the paper names E_k without a
 formula); mu_local follows the viscosity law of the run; the derivative of the
 Nyquist mode of an even-length axis is taken as zero.
+
+Shell spectrum (Section 3.2, the velocity spectra of the Taylor-Green run):
+shell-averaged, normalised so that its sum is <|u|^2>/2.  Readings: u is the
+velocity rho u / rho (not density-weighted); wavenumbers are the integers of
+the discrete Fourier transform on the cubic periodic box; a mode belongs to
+shell k = nint(|kappa|) (never a tie: |kappa|^2 is an integer and (k + 1/2)^2
+is not); every mode is counted, corners beyond N/2 included, so the sum is
+exact by Parseval's identity.
 """
 from __future__ import annotations
 
@@ -66,3 +74,23 @@ def sensor_fraction(f, prm):
     feq = lbm.equilibrium(Q, lbm.flux(Q, prm), prm)
     _, chi = lbm.relaxation_rate(f, feq, Q, prm)
     return float(np.mean(chi > 0.0))
+
+
+def spectrum_shells(n):
+    """Number of shells of an n^3 box: 1 + nint(sqrt(3) * (n // 2))."""
+    m = n // 2
+    return int(np.floor(np.sqrt(3.0 * m * m) + 0.5)) + 1
+
+
+def shell_spectrum(Q, prm):
+    """E(k) = 1/2 sum over modes with nint(|kappa|) = k of sum_c |u_hat_c(kappa)|^2,
+    u_hat = (1/N^3) DFT of the velocity, on a cubic periodic box."""
+    _, u, _, _, _ = lbm.primitives(Q, prm)
+    nz, ny, nx = u.shape[1:]
+    assert nx == ny == nz, "the shell spectrum is defined on a cubic box"
+    n = nx
+    m = np.fft.fftfreq(n, d=1.0 / n)
+    k2 = m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2
+    shell = np.floor(np.sqrt(k2) + 0.5).astype(np.int64)
+    e = sum(np.abs(np.fft.fftn(u[c])) ** 2 for c in range(3)) / float(n) ** 6 / 2.0
+    return np.bincount(shell.ravel(), weights=e.ravel(), minlength=spectrum_shells(n))

@@ -329,6 +329,47 @@ def test_tgv_initial_diagnostics_closed_form():
     assert d["eps_d"] < 1e-28
 
 
+def _field_state(n, u, v, w, rho=None, p=1.0):
+    """Conserved state of a given velocity field on an n^3 periodic box (rho = 1, p = 1 by default)."""
+    prm = W.default_params(n, n, n)
+    rho = np.ones((n, n, n)) if rho is None else rho
+    return W.conserved(rho, u, v, w, p * np.ones((n, n, n)), prm["gamma"]), prm
+
+
+def test_shell_spectrum_single_modes_closed_form():
+    """Section 3.2 spectra: a cosine mode of amplitude A and integer wavevector kappa
+    puts A^2/4 (= <u^2>/2) in shell nint(|kappa|) and nothing elsewhere."""
+    n = 12
+    x = 2 * np.pi * np.arange(n) / n
+    z, y, xx = np.meshgrid(x, x, x, indexing="ij")
+    zero = np.zeros((n, n, n))
+    for (kx, ky, kz), shell in (((0, 3, 0), 3), ((1, 1, 0), 1), ((1, 1, 1), 2), ((2, 2, 1), 3), ((0, 0, 5), 5)):
+        A = 0.3
+        u = A * np.cos(kx * xx + ky * y + kz * z)
+        Q, prm = _field_state(n, u, zero, zero)
+        E = diagnostics.shell_spectrum(Q, prm)
+        want = np.zeros_like(E)
+        want[shell] = A * A / 4
+        assert np.max(np.abs(E - want)) < 1e-15, (kx, ky, kz)
+
+
+def test_shell_spectrum_tgv_start_and_parseval():
+    """The Taylor-Green start has all its energy, <|u|^2>/2 = 1/8, at |kappa| = sqrt(3)
+    (shell 2); on a random state the shells sum to <|u|^2>/2 computed in physical space."""
+    c = W.tgv(16)
+    E = diagnostics.shell_spectrum(c.Q0, c.params)
+    assert len(E) == 1 + int(np.floor(np.sqrt(3) * 8 + 0.5))
+    assert abs(E[2] - 0.125) < 1e-15 and np.sum(np.abs(E)) - E[2] < 1e-15
+    rng = np.random.default_rng(3)
+    n = 10
+    u, v, w = (rng.normal(size=(n, n, n)) for _ in range(3))
+    rho = 1.0 + 0.2 * rng.random((n, n, n))
+    Q, prm = _field_state(n, u, v, w, rho=rho)
+    E = diagnostics.shell_spectrum(Q, prm)
+    assert abs(E.sum() - 0.5 * np.mean(u * u + v * v + w * w)) < 1e-13 * E.sum()
+    assert np.all(E >= 0.0)
+
+
 # --------------------------------------------------------------- P9 Sod
 def test_exact_riemann_star_state_matches_textbook():
     g = json.load(open(os.path.join(GOLDEN, "sod_star_textbook.json")))
