@@ -101,6 +101,45 @@ def second_allocation_ms(cnsf, L, prm, steps, warmup):
     return ms
 
 
+SPECTRUM_BYTES_PER_CELL = {"fp32": 688, "fp16": 492, "bf16": 492}
+
+
+def spectrum_timing(L, storage, reps=3):
+    """Shell-averaged velocity spectrum of the current state: mean time of one call
+    (velocity readout, three 3D transforms, shell sums), from HIP events on the
+    lattice's stream.  Algorithmic bytes per cell: the 98 populations read and
+    u, v, w, mu written (424 B FP32, 228 B 16-bit), 256 B for the axis passes,
+    8 B for the shell sums."""
+    import torch
+    E = L.spectrum(device=True)          # allocates the workspace
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        E = L.spectrum(device=True)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    gbps = SPECTRUM_BYTES_PER_CELL[storage] * L.ncells / (ms * 1e-3) / 1e9
+    return dict(ms=round(ms, 3), shells=int(E.numel()), GBps=round(gbps, 1),
+                frac_peak=round(gbps / PEAK_HBM_GBPS, 4), sum_E=float(E.sum().item()))
+
+
+def diagnostics_timing(L, reps=3):
+    """FP64 Eq. (7) diagnostics with spectral derivatives (sums, E_k, eps_s,
+    eps_d): mean time of one call, HIP events on the lattice's stream."""
+    import torch
+    L.diagnostics(spectral=True)         # allocates the workspace
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        L.diagnostics(spectral=True)
+    b.record()
+    torch.cuda.synchronize()
+    return round(a.elapsed_time(b) / reps, 3)
+
+
 def copy_bandwidth(cnsf, nbytes=8 << 30, reps=10):
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -185,6 +224,7 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-placement", action="store_true", help="skip the second-allocation timing")
+    ap.add_argument("--no-spectrum", action="store_true", help="skip the shell-spectrum timing")
     ap.add_argument("--copy-only", type=int, default=0, metavar="GIB",
                     help="only run the plain copy kernel on GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -207,6 +247,7 @@ def main():
     storages = list(STORAGES) if args.storage == "all" else [args.storage]
     head = "fp32" if "fp32" in storages else storages[0]
     placement = None
+    spectrum = None
     n = args.n
     Qdev = tgv_field_device(n)
     cells = n ** 3
@@ -219,6 +260,9 @@ def main():
         mean_ms, min_ms, wall = time_update(L, args.steps, args.warmup)
         if st == head and not args.no_placement:
             placement[0] = mean_ms
+        if st == head and not args.no_spectrum:
+            spectrum = spectrum_timing(L, st)
+            spectrum["diagnostics_ms"] = diagnostics_timing(L)
         d = L.diagnostics(spectral=False)
         alg_bytes = 98 * 2 * BYTES_PER_POP[st] * cells
         res[st] = dict(ms=mean_ms, min_ms=min_ms, wall=wall, mlups=cells / (mean_ms * 1e-3) / 1e6, launch=launch,
@@ -269,6 +313,8 @@ def main():
                      for st, v in res.items()},
         "kernel_hash": kernel_hash(),
     }
+    if spectrum is not None:
+        out["spectrum"] = dict(spectrum, storage=head)
     if placement is not None:
         out["placement"] = {"storage": head, "ms_per_step": [round(x, 4) for x in placement],
                             "note": "same state in two coexisting allocations; value is the first"}

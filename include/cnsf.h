@@ -167,6 +167,20 @@ int cnsf_get_moments(cnsf_lattice* lat, double* out, int32_t z0, int32_t nzs, in
  * first use, kept until cnsf_destroy). */
 int cnsf_diagnostics(cnsf_lattice* lat, int32_t flags, cnsf_diag* out);
 
+/* Shell-averaged velocity spectrum of the current time level (the spectra of
+ * Section 3.2): E[k] = 1/2 sum over wavevectors with nint(|kappa|) = k of
+ * sum_c |u_hat_c(kappa)|^2, u = rho u / rho, u_hat the discrete Fourier
+ * transform divided by the cell count, kappa integer on the cubic periodic
+ * box; every mode is counted, so sum_k E[k] = <|u|^2>/2.  FP64 throughout;
+ * the shell sums are taken in a fixed order (bitwise reproducible).
+ * cnsf_spectrum_shells gives the shell count 1 + nint(sqrt(3) * (n / 2)).
+ * E (host or device) holds nshells >= that count values; entries beyond it
+ * are zero.  Uses the spectral workspace of cnsf_diagnostics (allocated on
+ * first use) and nz * shells doubles more.  CNSF_E_INVALID unless nx = ny =
+ * nz with bc_x = PERIODIC; CNSF_E_SIZE if nshells is too small. */
+int cnsf_spectrum_shells(const cnsf_lattice* lat, int32_t* nshells);
+int cnsf_spectrum(cnsf_lattice* lat, double* E, int32_t nshells, int32_t where);
+
 /* Step counter, parity and the byte size of an exported checkpoint. */
 int cnsf_get_info(const cnsf_lattice* lat, int64_t* step, int32_t* parity, size_t* checkpoint_bytes);
 

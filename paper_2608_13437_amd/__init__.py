@@ -85,6 +85,8 @@ def library():
             "cnsf_step": [vp, i64],
             "cnsf_get_moments": [vp, dp, i32, i32, i32],
             "cnsf_diagnostics": [vp, i32, C.POINTER(cnsf_diag)],
+            "cnsf_spectrum_shells": [vp, C.POINTER(i32)],
+            "cnsf_spectrum": [vp, dp, i32, i32],
             "cnsf_get_info": [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(sz)],
             "cnsf_export_populations": [vp, vp, sz, C.POINTER(i64), C.POINTER(i32)],
             "cnsf_import_populations": [vp, vp, sz, i64, i32],
@@ -150,6 +152,16 @@ def cnsf_step(h, n: int):
 
 def cnsf_get_moments(h, out_ptr: int, z0: int, nzs: int, where: int):
     _check(library().cnsf_get_moments(h, C.cast(C.c_void_p(out_ptr), C.POINTER(C.c_double)), z0, nzs, where))
+
+
+def cnsf_spectrum_shells(h) -> int:
+    n = C.c_int32()
+    _check(library().cnsf_spectrum_shells(h, C.byref(n)))
+    return n.value
+
+
+def cnsf_spectrum(h, E_ptr: int, nshells: int, where: int) -> None:
+    _check(library().cnsf_spectrum(h, C.cast(C.c_void_p(E_ptr), C.POINTER(C.c_double)), nshells, where))
 
 
 def cnsf_diagnostics(h, flags: int) -> cnsf_diag:
@@ -284,6 +296,18 @@ class Lattice:
         return dict(step=d.step, time=d.time, mass=d.mass, momentum=list(d.momentum), energy=d.energy,
                     E_k=d.E_k, eps_s=d.eps_s, eps_d=d.eps_d, min_rho=d.min_rho, min_p=d.min_p,
                     sensor_fraction=d.sensor_fraction, nonfinite=d.nonfinite)
+
+    def spectrum(self, device: bool = False):
+        """Shell-averaged velocity spectrum E[k], k = 0 .. 1 + nint(sqrt(3) n / 2) - 1 (FP64)."""
+        k = cnsf_spectrum_shells(self.h)
+        if device:
+            torch = _torch()
+            out = torch.empty(k, dtype=torch.float64, device=self.device)
+            cnsf_spectrum(self.h, out.data_ptr(), k, CNSF_DEVICE)
+            return out
+        out = np.empty(k, dtype=np.float64)
+        cnsf_spectrum(self.h, out.ctypes.data, k, CNSF_HOST)
+        return out
 
     def info(self):
         return cnsf_get_info(self.h)

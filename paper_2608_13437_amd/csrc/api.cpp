@@ -230,6 +230,7 @@ struct cnsf_lattice {
   DiagPartial* partials = nullptr;    // diagnostics block partials
   DiagPartial* dresult = nullptr;
   double* fields = nullptr;           // spectral workspace (8 doubles per cell)
+  double* spec = nullptr;             // shell-spectrum partials and output
 };
 
 extern "C" {
@@ -310,6 +311,7 @@ int cnsf_destroy(cnsf_lattice* L) {
   if (L->partials) (void)hipFree(L->partials);
   if (L->dresult) (void)hipFree(L->dresult);
   if (L->fields) (void)hipFree(L->fields);
+  if (L->spec) (void)hipFree(L->spec);
   delete L;
   return CNSF_OK;
 }
@@ -431,6 +433,51 @@ int cnsf_diagnostics(cnsf_lattice* L, int32_t flags, cnsf_diag* d) {
   d->min_p = r.min_p;
   d->sensor_fraction = r.sensor / n;
   d->nonfinite = (int64_t)r.nonfinite;
+  return CNSF_OK;
+}
+
+int cnsf_spectrum_shells(const cnsf_lattice* L, int32_t* nshells) {
+  if (!L || !nshells) return fail(CNSF_E_INVALID, "NULL argument");
+  if (L->g.nx != L->g.ny || L->g.nx != L->g.nz || L->g.bc_x != CNSF_BC_PERIODIC)
+    return fail(CNSF_E_INVALID, "the shell spectrum needs a cubic periodic lattice");
+  *nshells = (int32_t)spectrum_shells(L->g.nx);
+  return CNSF_OK;
+}
+
+int cnsf_spectrum(cnsf_lattice* L, double* E, int32_t nshells, int32_t where) {
+  if (!L || !E) return fail(CNSF_E_INVALID, "NULL argument");
+  int32_t need = 0;
+  if (int r = cnsf_spectrum_shells(L, &need)) return r;
+  if (nshells < need) return fail(CNSF_E_SIZE, "spectrum needs %d shells, got %d", need, nshells);
+  if (where != CNSF_HOST && where != CNSF_DEVICE) return fail(CNSF_E_INVALID, "where must be HOST or DEVICE");
+  (void)hipSetDevice(L->device);
+  hipError_t e = hipSuccess;
+  if (!L->fields) {
+    e = hipMalloc(&L->fields, (size_t)8 * L->g.ncells * sizeof(double));
+    if (e != hipSuccess) {
+      L->fields = nullptr;
+      return fail(CNSF_E_NOMEM, "spectral workspace: %s", hipGetErrorString(e));
+    }
+  }
+  const size_t npart = (size_t)L->g.nz * (size_t)need;
+  if (!L->spec) {
+    e = hipMalloc(&L->spec, (npart + (size_t)need) * sizeof(double));
+    if (e != hipSuccess) {
+      L->spec = nullptr;
+      return fail(CNSF_E_NOMEM, "spectrum partials: %s", hipGetErrorString(e));
+    }
+  }
+  double* dE = where == CNSF_DEVICE ? E : L->spec + npart;
+  const uint32_t nout = where == CNSF_DEVICE ? (uint32_t)nshells : (uint32_t)need;
+  e = launch_diag_sums(L->p.storage, L->pop, L->g, L->ph, L->phd, L->cd, L->parity, L->partials, L->fields,
+                       L->stream);
+  if (e == hipSuccess) e = launch_spectrum(L->g, L->fields, L->spec, dE, nout, L->stream);
+  if (e == hipSuccess && where == CNSF_HOST) {
+    e = hipMemcpyAsync(E, dE, (size_t)need * sizeof(double), hipMemcpyDeviceToHost, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    for (int32_t k = need; k < nshells; ++k) E[k] = 0.0;
+  }
+  if (e != hipSuccess) return hip_fail(e, "spectrum");
   return CNSF_OK;
 }
 

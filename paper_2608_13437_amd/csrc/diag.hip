@@ -11,6 +11,8 @@
 // transformed back; derivatives accumulate into div u and curl u.  The last
 // axis also reduces mu |curl u|^2 and mu (div u)^2 into the block partials.
 // Pass 5 reduces the block partials in a fixed order (deterministic).
+#include <cmath>
+
 #include "cnsf_impl.h"
 #include "launch.h"
 
@@ -149,37 +151,74 @@ __device__ inline uint32_t line_base(uint32_t l, int axis, const Geom& g) {
 
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
 
-// In-place radix-2 transform of `cnt` lines of length n held in LDS, bit-reversed
-// input (forward, DIT) or natural input (inverse, DIF).  sign = -1 forward, +1 inverse.
-__device__ inline void fft_dit(double2* buf, uint32_t n, uint32_t log2n, uint32_t cnt) {
-  const uint32_t half = n / 2;
-  for (uint32_t h = 1; h < n; h <<= 1) {
-    for (uint32_t t = threadIdx.x; t < cnt * half; t += blockDim.x) {
-      const uint32_t line = t / half, b = t % half;
-      const uint32_t m = b % h, j = (b / h) * 2 * h + m;
-      double s, c;
-      sincospi(-(double)m / (double)h, &s, &c);
-      double2* L = buf + line * n;
-      const double2 x0 = L[j], x1 = cmul(make_double2(c, s), L[j + h]);
-      L[j] = make_double2(x0.x + x1.x, x0.y + x1.y);
-      L[j + h] = make_double2(x0.x - x1.x, x0.y - x1.y);
+// Line groups per block, XCD-contiguous: the hardware deals blocks
+// round-robin over the 8 XCDs, and gridDim.x is a multiple of 8, so XCD j
+// (blocks b = j mod 8) walks the j-th eighth of the groups in order.  In the
+// y and z passes neighbouring groups read neighbouring x, i.e. the same cache
+// lines, which then stay in one L2.
+struct GroupRange {
+  uint32_t begin, end, step;
+};
+__device__ inline GroupRange xcd_groups(uint32_t groups) {
+  const uint32_t x = blockIdx.x & 7u, per = (groups + 7u) / 8u;
+  GroupRange r;
+  r.begin = x * per + (blockIdx.x >> 3);
+  r.end = min(groups, (x + 1u) * per);
+  r.step = gridDim.x >> 3;
+  return r;
+}
+
+// LDS layout of a line: element p at p + p/8 (one 16-byte pad per 128 bytes),
+// so the power-of-two strides of the bit-reversed loads and of the butterflies
+// spread over all banks.
+__device__ inline uint32_t lds_idx(uint32_t p) { return p + (p >> 3); }
+__host__ __device__ inline uint32_t lds_line(uint32_t n) { return n + (n >> 3); }
+
+// Per-stage twiddles: stage h (a power of two) keeps exp(-i pi m / h), m < h,
+// at tw[h - 1 + m]; n - 1 entries, filled once per block.
+__device__ inline void fill_twiddles(double2* tw, uint32_t n) {
+  for (uint32_t q = threadIdx.x; q + 1 < n; q += blockDim.x) {
+    const uint32_t h = 1u << (31 - __clz(q + 1)), m = q + 1 - h;
+    double s, c;
+    sincospi(-(double)m / (double)h, &s, &c);
+    tw[q] = make_double2(c, s);
+  }
+}
+
+// In-place radix-2 transform of `cnt` lines of length n = 2^log2n held in LDS
+// (line stride lds_line(n)), bit-reversed input (forward, DIT) or natural
+// input (inverse, DIF, output bit-reversed).  Index arithmetic is shifts and
+// masks; the inverse uses the conjugate twiddles.
+__device__ inline void fft_dit(double2* buf, uint32_t n, uint32_t log2n, uint32_t cnt, const double2* tw) {
+  const uint32_t lh = log2n - 1, hmask = (n >> 1) - 1u, total = cnt << lh, np = lds_line(n);
+  for (uint32_t s = 0; s < log2n; ++s) {
+    const uint32_t h = 1u << s;
+    for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) {
+      const uint32_t b = t & hmask;
+      const uint32_t m = b & (h - 1u), j = ((b >> s) << (s + 1)) + m;
+      double2* L = buf + (t >> lh) * np;
+      const uint32_t i0 = lds_idx(j), i1 = lds_idx(j + h);
+      const double2 x0 = L[i0], x1 = cmul(tw[h - 1 + m], L[i1]);
+      L[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
+      L[i1] = make_double2(x0.x - x1.x, x0.y - x1.y);
     }
     __syncthreads();
   }
 }
 
-__device__ inline void fft_dif_inv(double2* buf, uint32_t n, uint32_t log2n, uint32_t cnt) {
-  const uint32_t half = n / 2;
-  for (uint32_t h = half; h >= 1; h >>= 1) {
-    for (uint32_t t = threadIdx.x; t < cnt * half; t += blockDim.x) {
-      const uint32_t line = t / half, b = t % half;
-      const uint32_t m = b % h, j = (b / h) * 2 * h + m;
-      double s, c;
-      sincospi((double)m / (double)h, &s, &c);
-      double2* L = buf + line * n;
-      const double2 x0 = L[j], x1 = L[j + h];
-      L[j] = make_double2(x0.x + x1.x, x0.y + x1.y);
-      L[j + h] = cmul(make_double2(x0.x - x1.x, x0.y - x1.y), make_double2(c, s));
+__device__ inline void fft_dif_inv(double2* buf, uint32_t n, uint32_t log2n, uint32_t cnt, const double2* tw) {
+  const uint32_t lh = log2n - 1, hmask = (n >> 1) - 1u, total = cnt << lh, np = lds_line(n);
+  for (int s = (int)lh; s >= 0; --s) {
+    const uint32_t h = 1u << s;
+    for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) {
+      const uint32_t b = t & hmask;
+      const uint32_t m = b & (h - 1u), j = ((b >> s) << (s + 1)) + m;
+      double2* L = buf + (t >> lh) * np;
+      const uint32_t i0 = lds_idx(j), i1 = lds_idx(j + h);
+      const double2 x0 = L[i0], x1 = L[i1];
+      const double2 w = tw[h - 1 + m];
+      L[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
+      L[i1] = cmul(make_double2(x0.x - x1.x, x0.y - x1.y), make_double2(w.x, -w.y));
     }
     __syncthreads();
   }
@@ -199,12 +238,15 @@ __global__ void __launch_bounds__(DB) k_spectral_axis(double* __restrict__ field
   const int a = ag.axis;
   const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;  // eps_{b2 a b1} = +1, eps_{b1 a b2} = -1
   const bool pow2 = ag.log2n != 0;
-  double2* A = lds;            // u_a + i u_b1
-  double2* B = lds + TL * n;   // u_b2 + i 0
+  const uint32_t np = lds_line(n);
+  double2* A = lds;             // u_a + i u_b1
+  double2* B = lds + TL * np;   // u_b2 + i 0
   // direct path (non power of two): separate output rows and the derivative kernel
-  double2* Aout = pow2 ? A : lds + 2 * TL * n;
-  double2* Bout = pow2 ? B : lds + 3 * TL * n;
-  double* Dk = (double*)(lds + (pow2 ? 2 : 4) * TL * n);
+  double2* Aout = pow2 ? A : lds + 2 * TL * np;
+  double2* Bout = pow2 ? B : lds + 3 * TL * np;
+  double2* tw = lds + 2 * TL * np;                       // power of two
+  double* Dk = (double*)(lds + 4 * TL * np);             // direct
+  if (pow2) fill_twiddles(tw, n);
   if (!pow2) {
     // D[m] = -(2/n) sum_{k=1}^{K} kappa_k sin(2 pi k m / n), Nyquist excluded
     const uint32_t K = (n % 2) ? (n - 1) / 2 : n / 2 - 1;
@@ -216,8 +258,8 @@ __global__ void __launch_bounds__(DB) k_spectral_axis(double* __restrict__ field
   }
   DiagPartial acc;
   part_zero(acc);
-  const uint32_t groups = (ag.nlines + TL - 1) / TL;
-  for (uint32_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+  const GroupRange gr = xcd_groups((ag.nlines + TL - 1) / TL);
+  for (uint32_t grp = gr.begin; grp < gr.end; grp += gr.step) {
     const uint32_t l0 = grp * TL;
     const uint32_t cnt = min(TL, ag.nlines - l0);
     __syncthreads();
@@ -228,39 +270,39 @@ __global__ void __launch_bounds__(DB) k_spectral_axis(double* __restrict__ field
       else { line = e % cnt; j = e / cnt; }
       const uint32_t addr = line_base(l0 + line, a, g) + j * ag.stride;
       const uint32_t pos = pow2 ? (__brev(j) >> (32 - ag.log2n)) : j;
-      A[line * n + pos] = make_double2(u[a][addr], u[b1][addr]);
-      B[line * n + pos] = make_double2(u[b2][addr], 0.0);
+      A[line * np + lds_idx(pos)] = make_double2(u[a][addr], u[b1][addr]);
+      B[line * np + lds_idx(pos)] = make_double2(u[b2][addr], 0.0);
     }
     __syncthreads();
     if (pow2) {
-      fft_dit(A, n, ag.log2n, cnt);
-      fft_dit(B, n, ag.log2n, cnt);
+      fft_dit(A, n, ag.log2n, cnt, tw);
+      fft_dit(B, n, ag.log2n, cnt, tw);
       // multiply by i kappa_j (Nyquist to zero) and 1/n for the inverse
       for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
-        const uint32_t j = e % n;
+        const uint32_t j = e & (n - 1u), q = (e >> ag.log2n) * np + lds_idx(j);
         double kj = (j < n / 2) ? (double)j : (j == n / 2 ? 0.0 : (double)j - (double)n);
         kj *= ag.kscale / (double)n;
-        const double2 x = A[e], y = B[e];
-        A[e] = make_double2(-kj * x.y, kj * x.x);
-        B[e] = make_double2(-kj * y.y, kj * y.x);
+        const double2 x = A[q], y = B[q];
+        A[q] = make_double2(-kj * x.y, kj * x.x);
+        B[q] = make_double2(-kj * y.y, kj * y.x);
       }
       __syncthreads();
-      fft_dif_inv(A, n, ag.log2n, cnt);   // output in bit-reversed positions
-      fft_dif_inv(B, n, ag.log2n, cnt);
+      fft_dif_inv(A, n, ag.log2n, cnt, tw);   // output in bit-reversed positions
+      fft_dif_inv(B, n, ag.log2n, cnt, tw);
     } else {
       // direct: d_j = sum_m D[m] x_{(j - m) mod n}
       for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
         const uint32_t line = e / n, j = e % n;
         double da = 0.0, db1 = 0.0, db2 = 0.0;
         for (uint32_t m = 0; m < n; ++m) {
-          const uint32_t src = line * n + (j + n - m) % n;
+          const uint32_t src = line * np + lds_idx((j + n - m) % n);
           const double d = Dk[m];
           da += d * A[src].x;
           db1 += d * A[src].y;
           db2 += d * B[src].x;
         }
-        Aout[e] = make_double2(da, db1);
-        Bout[e] = make_double2(db2, 0.0);
+        Aout[line * np + lds_idx(j)] = make_double2(da, db1);
+        Bout[line * np + lds_idx(j)] = make_double2(db2, 0.0);
       }
       __syncthreads();
     }
@@ -271,8 +313,8 @@ __global__ void __launch_bounds__(DB) k_spectral_axis(double* __restrict__ field
       else { line = e % cnt; j = e / cnt; }
       const uint32_t addr = line_base(l0 + line, a, g) + j * ag.stride;
       const uint32_t pos = pow2 ? (__brev(j) >> (32 - ag.log2n)) : j;
-      const double2 ra = Aout[line * n + pos];
-      const double dua = ra.x, dub1 = ra.y, dub2 = Bout[line * n + pos].x;
+      const double2 ra = Aout[line * np + lds_idx(pos)];
+      const double dua = ra.x, dub1 = ra.y, dub2 = Bout[line * np + lds_idx(pos)].x;
       // omega_{b2} += d_a u_{b1};  omega_{b1} -= d_a u_{b2}
       double dv = dua;
       const double wb2 = dub1, wb1 = -dub2;
@@ -302,6 +344,137 @@ __global__ void __launch_bounds__(DB) k_spectral_axis(double* __restrict__ field
       partials[blockIdx.x].eps_d = tot.eps_d;
     }
   }
+}
+
+// ------------------------------------------------------------------ shell spectrum
+// Forward transform along one axis of the velocity component being processed:
+// mode 0 reads the real field and writes complex, mode 1 transforms the complex
+// workspace in place, mode 2 transforms and stores (or adds) |X|^2 * escale
+// into the energy field.  Powers of two use the LDS radix-2 transform; other
+// lengths a direct sum.
+struct SpecAxis {
+  uint32_t n, stride, nlines, lines_per_block, log2n;
+  int axis;
+  int mode;
+  int accumulate;
+  double escale;
+};
+
+__global__ void __launch_bounds__(DB) k_spectrum_axis(const double* __restrict__ real_in, double2* __restrict__ data,
+                                                      double* __restrict__ energy, const Geom g, const SpecAxis sa) {
+  extern __shared__ double2 lds[];
+  const uint32_t n = sa.n, TL = sa.lines_per_block;
+  const bool pow2 = sa.log2n != 0;
+  const uint32_t np = lds_line(n);
+  double2* A = lds;
+  double2* Aout = pow2 ? A : lds + TL * np;
+  double2* tw = lds + TL * np;                           // power of two
+  if (pow2) fill_twiddles(tw, n);
+  const GroupRange gr = xcd_groups((sa.nlines + TL - 1) / TL);
+  for (uint32_t grp = gr.begin; grp < gr.end; grp += gr.step) {
+    const uint32_t l0 = grp * TL;
+    const uint32_t cnt = min(TL, sa.nlines - l0);
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
+      uint32_t line, j;
+      if (sa.axis == 0) { line = e / n; j = e % n; }
+      else { line = e % cnt; j = e / cnt; }
+      const uint32_t addr = line_base(l0 + line, sa.axis, g) + j * sa.stride;
+      const uint32_t pos = pow2 ? (__brev(j) >> (32 - sa.log2n)) : j;
+      A[line * np + lds_idx(pos)] = sa.mode == 0 ? make_double2(real_in[addr], 0.0) : data[addr];
+    }
+    __syncthreads();
+    if (pow2) {
+      fft_dit(A, n, sa.log2n, cnt, tw);   // natural-order output
+    } else {
+      for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
+        const uint32_t line = e / n, k = e % n;
+        double re = 0.0, im = 0.0;
+        for (uint32_t m = 0; m < n; ++m) {
+          double sn, cs;
+          sincospi(-2.0 * (double)((uint64_t)k * m % n) / (double)n, &sn, &cs);
+          const double2 x = A[line * np + lds_idx(m)];
+          re += x.x * cs - x.y * sn;
+          im += x.x * sn + x.y * cs;
+        }
+        Aout[line * np + lds_idx(k)] = make_double2(re, im);
+      }
+      __syncthreads();
+    }
+    for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
+      uint32_t line, j;
+      if (sa.axis == 0) { line = e / n; j = e % n; }
+      else { line = e % cnt; j = e / cnt; }
+      const uint32_t addr = line_base(l0 + line, sa.axis, g) + j * sa.stride;
+      const double2 X = Aout[line * np + lds_idx(j)];
+      if (sa.mode == 2) {
+        const double v = (X.x * X.x + X.y * X.y) * sa.escale;
+        energy[addr] = sa.accumulate ? energy[addr] + v : v;
+      } else {
+        data[addr] = X;
+      }
+    }
+  }
+}
+
+// Integer wavenumber of DFT index j on an axis of n points.
+__device__ inline int64_t wavenumber(uint32_t j, uint32_t n) { return j < (n + 1) / 2 ? (int64_t)j : (int64_t)j - n; }
+
+// Shell sums of one kappa_z plane per block, in a fixed order.  Along a row of
+// fixed (kappa_y, kappa_z) the shell nint(|kappa|) never decreases with
+// |kappa_x|, so a wave takes 64 consecutive |kappa_x| (both signs together),
+// sums each run of equal shells with a segmented scan, and adds the run totals
+// to its own LDS histogram (shells within one chunk are distinct).  Wave w
+// takes rows w, w + 4, ...; the block adds its four histograms in order.
+__global__ void __launch_bounds__(DB) k_shell_partials(const double* __restrict__ energy, uint32_t n, uint32_t nshells,
+                                                       double* __restrict__ partial) {
+  extern __shared__ double hist[];   // 4 x nshells
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  for (uint32_t s = threadIdx.x; s < 4 * nshells; s += blockDim.x) hist[s] = 0.0;
+  __syncthreads();
+  const uint32_t jz = blockIdx.x;
+  const int64_t mz = wavenumber(jz, n);
+  const uint32_t tmax = n / 2;      // largest |kappa_x|
+  double* h = hist + wave * nshells;
+  for (uint32_t jy = wave; jy < n; jy += 4) {
+    const int64_t my = wavenumber(jy, n);
+    const int64_t c2 = my * my + mz * mz;
+    const double* row = energy + ((uint64_t)jz * n + jy) * n;
+    for (uint32_t t0 = 0; t0 <= tmax; t0 += 64) {
+      const uint32_t t = t0 + lane;
+      const bool valid = t <= tmax;
+      int key = 0x7fffffff;
+      double val = 0.0;
+      if (valid) {
+        key = (int)floor(sqrt((double)((int64_t)t * t + c2)) + 0.5);
+        val = row[t];
+        if (t != 0 && n - t != t) val += row[n - t];
+      }
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const double ov = __shfl_up(val, d, 64);
+        const int ok = __shfl_up(key, d, 64);
+        if ((int)lane >= d && ok == key) val += ov;
+      }
+      const int next = __shfl_down(key, 1, 64);
+      if (valid && (lane == 63 || next != key)) h[key] += val;
+    }
+  }
+  __syncthreads();
+  for (uint32_t s = threadIdx.x; s < nshells; s += blockDim.x)
+    partial[(uint64_t)jz * nshells + s] = ((hist[s] + hist[nshells + s]) + hist[2 * nshells + s]) + hist[3 * nshells + s];
+}
+
+// E[k] = sum over planes of the partial shell sums, planes in order; zero for
+// k >= nshells up to nout.
+__global__ void k_shell_final(const double* __restrict__ partial, uint32_t nplanes, uint32_t nshells, uint32_t nout,
+                              double* __restrict__ E) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nout) return;
+  double acc = 0.0;
+  if (k < nshells)
+    for (uint32_t p = 0; p < nplanes; ++p) acc += partial[(uint64_t)p * nshells + k];
+  E[k] = acc;
 }
 
 __global__ void k_diag_final(const DiagPartial* __restrict__ partials, int nparts, DiagPartial* __restrict__ out) {
@@ -343,19 +516,66 @@ hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial
     uint32_t lg = 0;
     while ((1u << lg) < ag.n) ++lg;
     ag.log2n = ((1u << lg) == ag.n && ag.n >= 2) ? lg : 0;
-    // LDS: 2 (FFT) or 4 (direct) complex rows per line plus the kernel, <= 64 KiB
+    // LDS: 2 (FFT) or 4 (direct) complex rows per line, plus the twiddle
+    // table (FFT) or the derivative kernel (direct), <= 64 KiB
     const uint32_t rows = ag.log2n ? 2u : 4u;
-    uint32_t tl = (65536u - (ag.n + 2) * 8u) / (rows * ag.n * 16u);
+    const uint32_t extra = ag.log2n ? (ag.n - 1) * 16u : (ag.n + 2) * 8u;
+    uint32_t tl = (65536u - extra) / (rows * lds_line(ag.n) * 16u);
     ag.lines_per_block = tl < 1 ? 1 : (tl > 16 ? 16 : tl);
     ag.axis = a;
     ag.last = (a == 2);
     ag.kscale = 2.0 * M_PI / ((double)ag.n * dx);
-    const size_t lds = (size_t)rows * ag.lines_per_block * ag.n * sizeof(double2) + (size_t)(ag.n + 2) * sizeof(double);
+    const size_t lds = (size_t)rows * ag.lines_per_block * lds_line(ag.n) * sizeof(double2) + extra;
     hipLaunchKernelGGL(k_spectral_axis, dim3(DIAG_BLOCKS), dim3(DB), lds, s, fields, g, ag, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+uint32_t spectrum_shells(uint32_t n) {
+  const double m = (double)(n / 2);
+  return (uint32_t)std::floor(std::sqrt(3.0 * m * m) + 0.5) + 1u;
+}
+
+hipError_t launch_spectrum(const Geom& g, double* fields, double* partial, double* E, uint32_t nout, hipStream_t s) {
+  const uint32_t n = g.nx;
+  const uint64_t N = g.ncells;
+  const uint32_t nshells = spectrum_shells(n);
+  double2* data = (double2*)(fields + 4 * N);
+  double* energy = fields + 6 * N;
+  const uint32_t strides[3] = {1u, g.nx, g.nxy};
+  uint32_t lg = 0;
+  while ((1u << lg) < n) ++lg;
+  const uint32_t log2n = ((1u << lg) == n && n >= 2) ? lg : 0;
+  const uint32_t rows = log2n ? 1u : 2u;
+  const uint32_t extra = log2n ? (n - 1) * 16u : 0u;   // twiddle table
+  uint32_t tl = (65536u - extra) / (rows * lds_line(n) * 16u);
+  tl = tl < 1 ? 1 : (tl > 16 ? 16 : tl);
+  const size_t lds = (size_t)rows * tl * lds_line(n) * sizeof(double2) + extra;
+  const double n3 = (double)N;
+  for (int c = 0; c < 3; ++c) {
+    for (int a = 0; a < 3; ++a) {
+      SpecAxis sa{};
+      sa.n = n;
+      sa.stride = strides[a];
+      sa.nlines = (uint32_t)(N / n);
+      sa.lines_per_block = tl;
+      sa.log2n = log2n;
+      sa.axis = a;
+      sa.mode = a;
+      sa.accumulate = c > 0;
+      sa.escale = 0.5 / (n3 * n3);
+      hipLaunchKernelGGL(k_spectrum_axis, dim3(DIAG_BLOCKS), dim3(DB), lds, s, fields + c * N, data, energy, g, sa);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipLaunchKernelGGL(k_shell_partials, dim3(n), dim3(DB), 4 * nshells * sizeof(double), s, energy, n, nshells, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_shell_final, dim3((nout + 255) / 256), dim3(256), 0, s, partial, n, nshells, nout, E);
+  return hipGetLastError();
 }
 
 hipError_t launch_diag_final(DiagPartial* partials, int nparts, DiagPartial* out, hipStream_t s) {

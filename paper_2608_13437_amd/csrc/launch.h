@@ -40,5 +40,11 @@ hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const P
 // fields: u, v, w, mu (4 * ncells doubles), then div, wx, wy, wz (4 * ncells).
 hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial* partials, hipStream_t s);
 hipError_t launch_diag_final(DiagPartial* partials, int nparts, DiagPartial* out, hipStream_t s);
+// Shell spectrum of the velocity held in fields (u, v, w: the first 3 * ncells
+// doubles, written by launch_diag_sums); uses fields[4 ncells, 7 ncells) as
+// workspace and partial (nz * spectrum_shells(nx) doubles).  Writes nout
+// values to E (zero beyond the shell count).  Cubic periodic lattices only.
+uint32_t spectrum_shells(uint32_t n);
+hipError_t launch_spectrum(const Geom& g, double* fields, double* partial, double* E, uint32_t nout, hipStream_t s);
 
 }  // namespace cnsf

@@ -241,6 +241,58 @@ def test_slab_set_state_and_moments():
     assert rel_l2(full, Qo) < 1e-6
 
 
+# ------------------------------------------------------------------ shell spectrum
+def _spectrum_close(Eg, Eo):
+    # FP64 on both sides; transforms round differently, so compare against
+    # the total energy (and each shell's own size)
+    tot = float(np.sum(Eo))
+    return float(np.max(np.abs(Eg - Eo) / (1e-12 * tot + 1e-9 * np.abs(Eo))))
+
+
+def test_spectrum_tgv_start_closed_form():
+    """Taylor-Green start: all of <|u|^2>/2 = 1/8 in shell 2 (|kappa| = sqrt 3).
+    The lattice holds the field as FP32 populations, so the velocity is the
+    analytic one to FP32 rounding (relative 6e-8 per value): |E[2] - 1/8| is
+    bounded by 2 x 1.2e-7 x 1/8 = 3e-8."""
+    cnsf = _cnsf()
+    case = W.tgv(32)
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    E = L.spectrum()
+    log(f"case tgv32 t=0 spectrum: shells {len(E)}, E[2] = {E[2]!r}, rest {np.sum(np.abs(E)) - abs(E[2]):.2e}")
+    assert len(E) == 1 + int(np.floor(np.sqrt(3) * 16 + 0.5))
+    assert abs(E[2] - 0.125) < 3e-8
+    assert np.sum(np.abs(E)) - abs(E[2]) < 1e-14
+
+
+@pytest.mark.parametrize("case_fn,steps", [(lambda: W.tgv(32), 50), (lambda: W.tgv(128), 20),
+                                           (lambda: W.smooth_random_case(24, 24, 24, seed=4), 10)])
+def test_spectrum_matches_oracle(case_fn, steps):
+    """GPU shell spectrum vs the oracle's on the same state (radix-2 and direct transforms)."""
+    cnsf = _cnsf()
+    case = case_fn()
+    log(f"case {case.name} spectrum after {steps} steps")
+    L, Q = run_gpu(case, steps)
+    Eg = L.spectrum()
+    Eo = odiag.shell_spectrum(Q, case.params)
+    r = _spectrum_close(Eg, Eo)
+    log(f"  shells {len(Eg)}, sum {Eg.sum():.6e} vs {Eo.sum():.6e}, worst scaled difference {r:.3f}")
+    assert len(Eg) == len(Eo) and r <= 1.0
+    Ed = L.spectrum(device=True).cpu().numpy()
+    assert np.array_equal(Ed, Eg)                    # device output, and a second call, bitwise equal
+    assert np.array_equal(L.spectrum(), Eg)
+
+
+def test_spectrum_rejects_non_cubic_lattice():
+    cnsf = _cnsf()
+    case = W.random_case(13, 11, 9, seed=5)
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    with pytest.raises(cnsf.CnsfError) as e:
+        L.spectrum()
+    assert e.value.status == cnsf.CNSF_E_INVALID
+
+
 # ------------------------------------------------------------------ compressed storage
 @pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP16, 2e-3), (W.STORAGE_BF16, None)])
 def test_compressed_storage_error(storage, bound):
