@@ -1,0 +1,116 @@
+"""Taylor-Green runs on the GPU: Eq. (7) histories and shell spectra through the C ABI.
+
+usage:
+  python -m paper_2608_13437_amd.runs subsonic   [--n N] [--out PATH]
+  python -m paper_2608_13437_amd.runs supersonic [--n N] [--f-mu F] [--t-end T] [--out PATH]
+  python -m paper_2608_13437_amd.runs sweep      [--n N] [--f-mu F] [--C-sigma 10 20 40 80] [--out PATH]
+
+* subsonic: the shock-free verification case of Section 3.2 (Re 500, M0 0.5,
+  f_mu 0) to t_c = 10.
+* supersonic: the compressible case of Section 3.2 (Re 1600, M0 1.25, C_sigma 40,
+  J_min 1e-2, omega_min 1.987) with the given f_mu.
+* sweep: the supersonic case once per sensor slope C_sigma.
+
+Every step and every diagnostic runs in the HIP library; inputs come from the
+seeded generators of ``workloads``.  A run that turns non-finite stops and
+reports the time it happened.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+from . import Lattice  # noqa: E402
+
+HISTORY_KEYS = ("E_k", "eps_s", "eps_d", "mass", "energy", "min_rho", "min_p", "sensor_fraction")
+
+
+def tgv_run(n, *, t_end=None, steps=None, every=10, spectra_at=(), storage=W.STORAGE_FP32, slab=32, **tgv_kw):
+    """Run the Taylor-Green vortex on an n^3 lattice to t_end (convective times; or
+    for `steps` steps, a multiple of `every`), recording the FP64 diagnostics every
+    `every` steps and the shell spectrum at the recorded steps nearest to each
+    time in `spectra_at`."""
+    prm = W.tgv_params(n, storage=storage, **tgv_kw)
+    L = Lattice(prm)
+    for z0 in range(0, n, slab):
+        L.set_state(W.tgv_slab(prm, z0, min(n, z0 + slab)), z0=z0)
+    dt = prm["dt"]
+    if steps is None:
+        steps = int(math.ceil(t_end / dt / every)) * every
+    assert steps % every == 0
+    want = {int(round(t / dt / every)) * every: t for t in spectra_at}
+    hist = {"step": [], "t": []}
+    hist.update({k: [] for k in HISTORY_KEYS})
+    spectra = {}
+    status, t0 = "ok", time.perf_counter()
+    for s in range(0, steps + 1, every):
+        d = L.diagnostics(spectral=True)
+        hist["step"].append(s)
+        hist["t"].append(s * dt)
+        for k in HISTORY_KEYS:
+            hist[k].append(d[k])
+        if d["nonfinite"]:
+            status = f"non-finite at t_c = {s * dt:.3f}"
+            break
+        if s in want:
+            spectra[f"{s * dt:.4f}"] = L.spectrum().tolist()
+        if s < steps:
+            L.step(every)
+    wall = time.perf_counter() - t0
+    L.close()
+    done = hist["step"][-1]
+    case = dict(tgv_kw)
+    case.update(n=n, dt=dt, storage=storage)
+    case.update({k: prm[k] for k in ("f_mu", "C_sigma", "J_min", "omega_min", "mu0", "tau_R", "tau_q")})
+    return dict(case=case, every=every, steps=done, status=status, wall_seconds=round(wall, 2),
+                mlups_with_diagnostics=round(n ** 3 * done / wall / 1e6, 1) if wall > 0 else None,
+                history=hist, spectra=spectra)
+
+
+def summary(run):
+    h = run["history"]
+    i = max(range(len(h["eps_s"])), key=lambda j: h["eps_s"][j])
+    return (f"n {run['case']['n']} {run['status']}: t_c {h['t'][-1]:.2f} ({run['steps']} steps), "
+            f"peak eps_s {h['eps_s'][i]:.5e} at t_c {h['t'][i]:.2f}, max eps_d {max(h['eps_d']):.3e}, "
+            f"E_k end {h['E_k'][-1]:.5f}, {run['wall_seconds']} s")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("case", choices=("subsonic", "supersonic", "sweep"))
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--f-mu", type=float, default=None)
+    ap.add_argument("--C-sigma", type=float, nargs="+", default=[10.0, 20.0, 40.0, 80.0])
+    ap.add_argument("--t-end", type=float, default=None)
+    ap.add_argument("--every", type=int, default=10)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    runs = []
+    if a.case == "subsonic":
+        runs.append(tgv_run(a.n, t_end=a.t_end or 10.0, every=a.every, spectra_at=(0.0, 5.0, 10.0),
+                            M0=0.5, Re=500.0, f_mu=0.0 if a.f_mu is None else a.f_mu))
+    elif a.case == "supersonic":
+        runs.append(tgv_run(a.n, t_end=a.t_end or 20.0, every=a.every, spectra_at=(0.0, 9.0),
+                            f_mu=a.f_mu))
+    else:
+        for cs in a.C_sigma:
+            runs.append(tgv_run(a.n, t_end=a.t_end or 20.0, every=a.every, f_mu=a.f_mu, C_sigma=cs))
+    for r in runs:
+        print(summary(r), flush=True)
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(runs, fh)
+
+
+if __name__ == "__main__":
+    main()
