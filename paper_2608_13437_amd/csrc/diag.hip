@@ -87,15 +87,16 @@ __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* _
     const Nbr n = neighbours(c, g);
     uint32_t off[NV];
     stream_offsets<ST, BC>(g, n, parity, off);
-    double gv[NC][NV];
-    gather<ST, BC, true, double>(pop, g, cd, n, parity, off, gv);
+    // the stored values are FP32 or 16-bit: gather them in FP32 (exact), sum in FP64
+    float gf[NC][NV];
+    gather<ST, BC, true, float>(pop, g, cd, n, parity, off, gf);
     double Q[NC];
     bool finite = true;
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       double s = 0.0;
 #pragma unroll
-      for (int i = 0; i < NV; ++i) s += gv[k][i];
+      for (int i = 0; i < NV; ++i) s += (double)gf[k][i];
       Q[k] = q_ref<double>(cd, k) + s;
       finite = finite && isfinite(s);
     }
@@ -110,12 +111,8 @@ __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* _
     acc.min_p = fmin(acc.min_p, P.p);
     acc.nonfinite += finite ? 0.0 : 1.0;
     // the sensor decision as the FP32 update takes it
-    float gf[NC][NV], dQf[NC], Qf[NC];
+    float dQf[NC], Qf[NC];
     DevPrim Pf;
-#pragma unroll
-    for (int k = 0; k < NC; ++k)
-#pragma unroll
-      for (int i = 0; i < NV; ++i) gf[k][i] = (float)gv[k][i];
     float chi = 0.0f;
     cell_state(gf, cd, ph, dQf, Qf, Pf, &chi);
     acc.sensor += chi > 0.0f ? 1.0 : 0.0;
@@ -185,40 +182,91 @@ __device__ inline void fill_twiddles(double2* tw, uint32_t n) {
   }
 }
 
-// In-place radix-2 transform of `cnt` lines of length n = 2^log2n held in LDS
-// (line stride lds_line(n)), bit-reversed input (forward, DIT) or natural
-// input (inverse, DIF, output bit-reversed).  Index arithmetic is shifts and
-// masks; the inverse uses the conjugate twiddles.
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 conj2(double2 w) { return make_double2(w.x, -w.y); }
+
+// In-place transform of `cnt` lines of length n = 2^log2n held in LDS (line
+// stride lds_line(n)): forward decimation in time from bit-reversed input, or
+// inverse decimation in frequency from natural input (output bit-reversed).
+// Pairs of radix-2 stages are fused into one radix-4 step (four values per
+// thread, one LDS round trip and one barrier for two stages); the arithmetic
+// is that of the two stages in their order, so the result is the radix-2
+// transform's bit for bit.  An odd stage count ends with one radix-2 stage.
 __device__ inline void fft_dit(double2* buf, uint32_t n, uint32_t log2n, uint32_t cnt, const double2* tw) {
-  const uint32_t lh = log2n - 1, hmask = (n >> 1) - 1u, total = cnt << lh, np = lds_line(n);
-  for (uint32_t s = 0; s < log2n; ++s) {
-    const uint32_t h = 1u << s;
+  const uint32_t np = lds_line(n);
+  uint32_t s = 0;
+  if (log2n >= 2) {
+    const uint32_t lq = log2n - 2, qmask = (n >> 2) - 1u, totq = cnt << lq;
+    for (; s + 1 < log2n; s += 2) {
+      const uint32_t h = 1u << s;
+      for (uint32_t t = threadIdx.x; t < totq; t += blockDim.x) {
+        const uint32_t q = t & qmask;
+        const uint32_t m = q & (h - 1u), j = ((q >> s) << (s + 2)) + m;
+        double2* L = buf + (t >> lq) * np;
+        const uint32_t i0 = lds_idx(j), i1 = lds_idx(j + h), i2 = lds_idx(j + 2 * h), i3 = lds_idx(j + 3 * h);
+        const double2 a0 = L[i0], a1 = L[i1], a2 = L[i2], a3 = L[i3];
+        const double2 w1 = tw[h - 1 + m];
+        const double2 t1 = cmul(w1, a1), t3 = cmul(w1, a3);
+        const double2 b0 = cadd(a0, t1), b1 = csub(a0, t1), b2 = cadd(a2, t3), b3 = csub(a2, t3);
+        const double2 u2 = cmul(tw[2 * h - 1 + m], b2), u3 = cmul(tw[2 * h - 1 + m + h], b3);
+        L[i0] = cadd(b0, u2);
+        L[i2] = csub(b0, u2);
+        L[i1] = cadd(b1, u3);
+        L[i3] = csub(b1, u3);
+      }
+      __syncthreads();
+    }
+  }
+  if (s < log2n) {
+    const uint32_t lh = log2n - 1, hmask = (n >> 1) - 1u, total = cnt << lh, h = 1u << s;
     for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) {
       const uint32_t b = t & hmask;
       const uint32_t m = b & (h - 1u), j = ((b >> s) << (s + 1)) + m;
       double2* L = buf + (t >> lh) * np;
       const uint32_t i0 = lds_idx(j), i1 = lds_idx(j + h);
       const double2 x0 = L[i0], x1 = cmul(tw[h - 1 + m], L[i1]);
-      L[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
-      L[i1] = make_double2(x0.x - x1.x, x0.y - x1.y);
+      L[i0] = cadd(x0, x1);
+      L[i1] = csub(x0, x1);
     }
     __syncthreads();
   }
 }
 
 __device__ inline void fft_dif_inv(double2* buf, uint32_t n, uint32_t log2n, uint32_t cnt, const double2* tw) {
-  const uint32_t lh = log2n - 1, hmask = (n >> 1) - 1u, total = cnt << lh, np = lds_line(n);
-  for (int s = (int)lh; s >= 0; --s) {
-    const uint32_t h = 1u << s;
+  const uint32_t np = lds_line(n);
+  int s = (int)log2n - 1;
+  if (log2n >= 2) {
+    const uint32_t lq = log2n - 2, qmask = (n >> 2) - 1u, totq = cnt << lq;
+    for (; s >= 1; s -= 2) {
+      const uint32_t h = 1u << s, hh = h >> 1;
+      for (uint32_t t = threadIdx.x; t < totq; t += blockDim.x) {
+        const uint32_t q = t & qmask;
+        const uint32_t m = q & (hh - 1u), j = ((q >> (s - 1)) << (s + 1)) + m;
+        double2* L = buf + (t >> lq) * np;
+        const uint32_t i0 = lds_idx(j), i1 = lds_idx(j + hh), i2 = lds_idx(j + 2 * hh), i3 = lds_idx(j + 3 * hh);
+        const double2 a0 = L[i0], a1 = L[i1], a2 = L[i2], a3 = L[i3];
+        const double2 c0 = cadd(a0, a2), c2 = cmul(csub(a0, a2), conj2(tw[h - 1 + m]));
+        const double2 c1 = cadd(a1, a3), c3 = cmul(csub(a1, a3), conj2(tw[h - 1 + m + hh]));
+        const double2 w = conj2(tw[hh - 1 + m]);
+        L[i0] = cadd(c0, c1);
+        L[i1] = cmul(csub(c0, c1), w);
+        L[i2] = cadd(c2, c3);
+        L[i3] = cmul(csub(c2, c3), w);
+      }
+      __syncthreads();
+    }
+  }
+  if (s == 0) {
+    const uint32_t lh = log2n - 1, total = cnt << lh;
+    const double2 w = conj2(tw[0]);
     for (uint32_t t = threadIdx.x; t < total; t += blockDim.x) {
-      const uint32_t b = t & hmask;
-      const uint32_t m = b & (h - 1u), j = ((b >> s) << (s + 1)) + m;
+      const uint32_t j = (t & ((n >> 1) - 1u)) << 1;
       double2* L = buf + (t >> lh) * np;
-      const uint32_t i0 = lds_idx(j), i1 = lds_idx(j + h);
+      const uint32_t i0 = lds_idx(j), i1 = lds_idx(j + 1);
       const double2 x0 = L[i0], x1 = L[i1];
-      const double2 w = tw[h - 1 + m];
-      L[i0] = make_double2(x0.x + x1.x, x0.y + x1.y);
-      L[i1] = cmul(make_double2(x0.x - x1.x, x0.y - x1.y), make_double2(w.x, -w.y));
+      L[i0] = cadd(x0, x1);
+      L[i1] = cmul(csub(x0, x1), w);
     }
     __syncthreads();
   }
