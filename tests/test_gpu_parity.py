@@ -308,6 +308,50 @@ def test_compressed_storage_error(storage, bound):
         assert all(v < bound for v in err.values()), err
 
 
+@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP16, 2e-3), (W.STORAGE_BF16, 1.6e-2)])
+def test_scaled_storage_keeps_small_components(storage, bound):
+    """Per-component storage scales (stress and heat flux stored x 256).  FP16: the
+    small deviations of those components partly fall in the subnormal range,
+    and scaled they keep more bits, so their error against the oracle does not
+    grow.  BF16 has FP32's exponent range, so a power-of-two scale is exact and
+    the run is bitwise the unscaled one.  rho, u, T stay within the bound."""
+    case = W.tgv(32)
+    n = 100
+    scale = [1.0] * 5 + [2.0 ** -8] * 9
+    log(f"case tgv32 storage {storage} scaled tau, q by 2^-8, {n} steps")
+    _, Qu = run_gpu(case, n, storage=storage)
+    c2 = W.Case(case.name, dict(case.params, storage_scale=scale), case.Q0, case.steps)
+    _, Qs = run_gpu(c2, n, storage=storage)
+    Qo = run_oracle(case, n)
+    eu, es = compare(Qu, Qo, case.params), compare(Qs, Qo, case.params)
+    tq_u, tq_s = rel_l2(Qu[5:], Qo[5:]), rel_l2(Qs[5:], Qo[5:])
+    log(f"  unscaled {eu}, tau/q {tq_u:.3e};  scaled {es}, tau/q {tq_s:.3e}")
+    assert all(v < bound for v in es.values()), es
+    if storage == W.STORAGE_BF16:
+        assert np.array_equal(Qs, Qu)
+    else:
+        assert not np.array_equal(Qs, Qu) and tq_s <= tq_u
+
+
+def test_batch_with_scaled_members_matches_single_lattices():
+    cnsf = _cnsf()
+    scale = [1.0] * 5 + [2.0 ** -8] * 9
+    cases = [W.tgv(32, M0=0.8), W.tgv(24, M0=0.8)]
+    prms = [dict(c.params, storage=W.STORAGE_FP16, storage_scale=scale) for c in cases]
+    n = 12
+    B = cnsf.Batch(prms)
+    for j, c in enumerate(cases):
+        B.set_state(j, c.Q0)
+    B.step(n, 1)
+    for j, (c, p) in enumerate(zip(cases, prms)):
+        L = cnsf.Lattice(p)
+        L.set_state(c.Q0)
+        L.step(n)
+        assert np.array_equal(B.moments(j), L.moments()), f"member {j}"
+        L.close()
+    B.close()
+
+
 # ------------------------------------------------------------------ batch
 def test_batch_matches_single_lattices():
     cnsf = _cnsf()
