@@ -152,6 +152,12 @@ int cnsf_destroy(cnsf_lattice* lat);
  * p <= 0 or a non-finite value (checked on the device). */
 int cnsf_set_state(cnsf_lattice* lat, const double* Q, int32_t z0, int32_t nzs, int32_t where);
 
+/* As cnsf_set_state, from primitive fields: P (host or device) is
+ * [14][nzs][ny][nx] holding rho, u_x, u_y, u_z, p, tau_{xx,yy,zz,xy,xz,yz},
+ * q_{x,y,z}; the conserved state (rho, rho u, E = p/(gamma-1) + rho|u|^2/2,
+ * tau, q; Section 2.1) is formed on the device in FP64. */
+int cnsf_set_primitive(cnsf_lattice* lat, const double* P, int32_t z0, int32_t nzs, int32_t where);
+
 /* Enqueue n fused stream-and-collide updates (Section 2.2, with the sensor of
  * Section 2.3; alternating even/odd in-place passes).  Asynchronous; n >= 0.
  * CNSF_E_DEVICE if a launch fails. */
@@ -161,6 +167,12 @@ int cnsf_step(cnsf_lattice* lat, int64_t n);
  * level for z-planes [z0, z0+nzs), written FP64 to out (host or device) as
  * [14][nzs][ny][nx].  CNSF_E_SIZE if the slab leaves the lattice. */
 int cnsf_get_moments(cnsf_lattice* lat, double* out, int32_t z0, int32_t nzs, int32_t where);
+
+/* Primitive fields of the current time level for z-planes [z0, z0+nzs),
+ * written FP64 to out (host or device) as [6][nzs][ny][nx]: rho, u_x, u_y,
+ * u_z, p = (gamma-1)(E - rho|u|^2/2), T = p/rho (Section 2.1).
+ * CNSF_E_SIZE if the slab leaves the lattice. */
+int cnsf_get_primitives(cnsf_lattice* lat, double* out, int32_t z0, int32_t nzs, int32_t where);
 
 /* FP64 diagnostics of the current time level; flags: CNSF_DIAG_SUMS or
  * CNSF_DIAG_SPECTRAL (adds eps_s, eps_d; allocates eight FP64 cell fields on

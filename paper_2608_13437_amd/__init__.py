@@ -84,6 +84,8 @@ def library():
             "cnsf_set_state": [vp, dp, i32, i32, i32],
             "cnsf_step": [vp, i64],
             "cnsf_get_moments": [vp, dp, i32, i32, i32],
+            "cnsf_set_primitive": [vp, dp, i32, i32, i32],
+            "cnsf_get_primitives": [vp, dp, i32, i32, i32],
             "cnsf_diagnostics": [vp, i32, C.POINTER(cnsf_diag)],
             "cnsf_spectrum_shells": [vp, C.POINTER(i32)],
             "cnsf_spectrum": [vp, dp, i32, i32],
@@ -152,6 +154,14 @@ def cnsf_step(h, n: int):
 
 def cnsf_get_moments(h, out_ptr: int, z0: int, nzs: int, where: int):
     _check(library().cnsf_get_moments(h, C.cast(C.c_void_p(out_ptr), C.POINTER(C.c_double)), z0, nzs, where))
+
+
+def cnsf_set_primitive(h, P_ptr: int, z0: int, nzs: int, where: int):
+    _check(library().cnsf_set_primitive(h, C.cast(C.c_void_p(P_ptr), C.POINTER(C.c_double)), z0, nzs, where))
+
+
+def cnsf_get_primitives(h, out_ptr: int, z0: int, nzs: int, where: int):
+    _check(library().cnsf_get_primitives(h, C.cast(C.c_void_p(out_ptr), C.POINTER(C.c_double)), z0, nzs, where))
 
 
 def cnsf_spectrum_shells(h) -> int:
@@ -275,6 +285,27 @@ class Lattice:
             Q = np.ascontiguousarray(Q, dtype=np.float64)
             assert Q.shape[0] == NCOMP and Q.shape[2:] == self.shape[1:]
             cnsf_set_state(self.h, Q.ctypes.data, z0, Q.shape[1], CNSF_HOST)
+
+    def set_primitive(self, P, z0: int = 0):
+        """P: float64 (14, nzs, ny, nx): rho, u (3), p, tau (6), q (3); host array or CUDA tensor."""
+        torch = _torch()
+        if isinstance(P, torch.Tensor):
+            P = P.to(dtype=torch.float64).contiguous()
+            assert P.is_cuda and P.shape[0] == NCOMP
+            cnsf_set_primitive(self.h, P.data_ptr(), z0, P.shape[1], CNSF_DEVICE)
+            self._keep = P
+        else:
+            P = np.ascontiguousarray(P, dtype=np.float64)
+            assert P.shape[0] == NCOMP and P.shape[2:] == self.shape[1:]
+            cnsf_set_primitive(self.h, P.ctypes.data, z0, P.shape[1], CNSF_HOST)
+
+    def primitives(self, z0: int = 0, nzs: int | None = None):
+        """(6, nzs, ny, nx) FP64: rho, u_x, u_y, u_z, p, T of the current time level."""
+        if nzs is None:
+            nzs = self.p.nz - z0
+        out = np.empty((6, nzs, self.p.ny, self.p.nx), dtype=np.float64)
+        cnsf_get_primitives(self.h, out.ctypes.data, z0, nzs, CNSF_HOST)
+        return out
 
     def step(self, n: int = 1):
         cnsf_step(self.h, int(n))

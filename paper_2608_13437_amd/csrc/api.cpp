@@ -328,7 +328,7 @@ int cnsf_set_launch(cnsf_lattice* L, int32_t block, int32_t tile, int32_t grid, 
   return CNSF_OK;
 }
 
-int cnsf_set_state(cnsf_lattice* L, const double* Q, int32_t z0, int32_t nzs, int32_t where) {
+static int set_state_impl(cnsf_lattice* L, const double* Q, int32_t z0, int32_t nzs, int32_t where, bool prim) {
   if (!L || !Q) return fail(CNSF_E_INVALID, "NULL argument");
   if (z0 < 0 || nzs < 0 || z0 + nzs > (int)L->g.nz) return fail(CNSF_E_SIZE, "slab [%d, %d) outside nz = %u", z0, z0 + nzs, L->g.nz);
   if (where != CNSF_HOST && where != CNSF_DEVICE) return fail(CNSF_E_INVALID, "where = %d", where);
@@ -348,7 +348,8 @@ int cnsf_set_state(cnsf_lattice* L, const double* Q, int32_t z0, int32_t nzs, in
   }
   int bad = 0;
   e = hipMemsetAsync(L->dflag, 0, sizeof(int), L->stream);
-  if (e == hipSuccess) e = launch_init(L->p.storage, L->pop, dQ, L->g, L->phd, L->cd, cell0, nslab, L->dflag, L->stream);
+  if (e == hipSuccess)
+    e = launch_init(L->p.storage, L->pop, dQ, L->g, L->phd, L->cd, cell0, nslab, L->dflag, prim, L->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, L->dflag, sizeof(int), hipMemcpyDeviceToHost, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (tmp) (void)hipFree(tmp);
@@ -371,6 +372,38 @@ int cnsf_step(cnsf_lattice* L, int64_t n) {
     L->parity ^= 1;
     ++L->step;
   }
+  return CNSF_OK;
+}
+
+int cnsf_set_state(cnsf_lattice* L, const double* Q, int32_t z0, int32_t nzs, int32_t where) {
+  return set_state_impl(L, Q, z0, nzs, where, false);
+}
+
+int cnsf_set_primitive(cnsf_lattice* L, const double* P, int32_t z0, int32_t nzs, int32_t where) {
+  return set_state_impl(L, P, z0, nzs, where, true);
+}
+
+int cnsf_get_primitives(cnsf_lattice* L, double* out, int32_t z0, int32_t nzs, int32_t where) {
+  if (!L || !out) return fail(CNSF_E_INVALID, "NULL argument");
+  if (z0 < 0 || nzs < 0 || z0 + nzs > (int)L->g.nz) return fail(CNSF_E_SIZE, "slab [%d, %d) outside nz = %u", z0, z0 + nzs, L->g.nz);
+  if (where != CNSF_HOST && where != CNSF_DEVICE) return fail(CNSF_E_INVALID, "where = %d", where);
+  (void)hipSetDevice(L->device);
+  const uint32_t nslab = (uint32_t)nzs * L->g.nxy;
+  const uint32_t cell0 = (uint32_t)z0 * L->g.nxy;
+  const size_t pbytes = (size_t)6 * nslab * sizeof(double);
+  double* dst = out;
+  double* tmp = nullptr;
+  hipError_t e;
+  if (where == CNSF_HOST && nslab) {
+    e = hipMalloc(&tmp, pbytes);
+    if (e != hipSuccess) return fail(CNSF_E_NOMEM, "hipMalloc(%zu): %s", pbytes, hipGetErrorString(e));
+    dst = tmp;
+  }
+  e = launch_primitives(L->p.storage, L->pop, dst, L->g, L->cd, L->phd, L->parity, cell0, nslab, L->stream);
+  if (e == hipSuccess && tmp) e = hipMemcpyAsync(out, tmp, pbytes, hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "get_primitives");
   return CNSF_OK;
 }
 

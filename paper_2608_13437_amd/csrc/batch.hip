@@ -258,7 +258,7 @@ int cnsf_batch_set_state(cnsf_batch* b, int32_t j, const double* Q, int32_t wher
   int bad = 0;
   void* pop = (char*)b->base + M.pop_offset * elem_bytes(b->storage);
   if (e == hipSuccess) e = hipMemsetAsync(b->dflag, 0, sizeof(int), b->stream);
-  if (e == hipSuccess) e = launch_init(b->storage, pop, dQ, M.g, b->phd[j], M.cd, 0, M.g.ncells, b->dflag, b->stream);
+  if (e == hipSuccess) e = launch_init(b->storage, pop, dQ, M.g, b->phd[j], M.cd, 0, M.g.ncells, b->dflag, false, b->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(&bad, b->dflag, sizeof(int), hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (tmp) (void)hipFree(tmp);

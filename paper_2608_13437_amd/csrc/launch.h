@@ -22,7 +22,9 @@ Launch default_launch(int storage);
 hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
                          const Launch& lc, hipStream_t s);
 hipError_t launch_init(int storage, void* pop, const double* Q, const Geom& g, const PhysD& ph, const Codec& cd,
-                       uint32_t cell0, uint32_t nslab, int* bad, hipStream_t s);
+                       uint32_t cell0, uint32_t nslab, int* bad, bool primitive, hipStream_t s);
+hipError_t launch_primitives(int storage, const void* pop, double* out, const Geom& g, const Codec& cd, const PhysD& ph,
+                             int parity, uint32_t cell0, uint32_t nslab, hipStream_t s);
 hipError_t launch_moments(int storage, const void* pop, double* out, const Geom& g, const Codec& cd, int parity,
                           uint32_t cell0, uint32_t nslab, hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s);

@@ -58,8 +58,10 @@ __global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restric
   }
 }
 
-// f = f^eq(Q) for cells of z-planes [z0, z0 + nzs); FP64 arithmetic.
-template <int ST>
+// f = f^eq(Q) for cells of z-planes [z0, z0 + nzs); FP64 arithmetic.  With
+// PRIM the input holds rho, u (3), p, tau (6), q (3) per cell, turned into the
+// conserved state (ideal gas, Section 2.1) first.
+template <int ST, bool PRIM>
 __global__ void k_init(typename Store<ST>::T* __restrict__ pop, const double* __restrict__ Q, const Geom g,
                        const PhysD ph, const Codec cd, uint32_t cell0, uint32_t nslab, int* __restrict__ bad) {
   using S = Store<ST>;
@@ -69,6 +71,13 @@ __global__ void k_init(typename Store<ST>::T* __restrict__ pop, const double* __
   double q[NC];
 #pragma unroll
   for (int k = 0; k < NC; ++k) q[k] = Q[(uint64_t)k * nslab + j];
+  if (PRIM) {
+    const double rho = q[0], ux = q[1], uy = q[2], uz = q[3], p = q[4];
+    q[1] = rho * ux;
+    q[2] = rho * uy;
+    q[3] = rho * uz;
+    q[4] = p / ph.gm1 + 0.5 * rho * (ux * ux + uy * uy + uz * uz);
+  }
   Prim<double> P = primitives<double>(q, ph);
   bool ok = P.rho > 0.0 && P.p > 0.0;
 #pragma unroll
@@ -83,6 +92,31 @@ __global__ void k_init(typename Store<ST>::T* __restrict__ pop, const double* __
     for (int k = 0; k < NC; ++k)
       base[k * g.cstride] = S::enc((float)((feq[k][i] - feq_ref<double>(cd, k, i)) * (double)cd.inv_scale[k]));
   }
+}
+
+// rho, u (3), p, T of the current time level (FP64, from the FP64 moments).
+template <int ST, int BC>
+__global__ void k_primitives(const typename Store<ST>::T* __restrict__ pop, double* __restrict__ out, const Geom g,
+                             const Codec cd, const PhysD ph, int parity, uint32_t cell0, uint32_t nslab) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nslab) return;
+  const Nbr n = neighbours(cell0 + j, g);
+  uint32_t off[NV];
+  stream_offsets<ST, BC>(g, n, parity, off);
+  float gf[NC][NV];
+  gather<ST, BC, true, float>(pop, g, cd, n, parity, off, gf);
+  double Q[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) s += (double)gf[k][i];
+    Q[k] = q_ref<double>(cd, k) + s;
+  }
+  const Prim<double> P = primitives<double>(Q, ph);
+  const double v[6] = {P.rho, P.u[0], P.u[1], P.u[2], P.p, P.T};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) out[(uint64_t)k * nslab + j] = v[k];
 }
 
 // Q_k = sum_i f_{k,i} of the current time level (FP64 accumulation).
@@ -149,18 +183,42 @@ hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, 
   return hipErrorInvalidValue;
 }
 
+template <int ST, bool PRIM>
+static void init_t(void* pop, const double* Q, const Geom& g, const PhysD& ph, const Codec& cd, uint32_t cell0,
+                   uint32_t nslab, int* bad, uint32_t nb, hipStream_t s) {
+  hipLaunchKernelGGL((k_init<ST, PRIM>), dim3(nb), dim3(256), 0, s, (typename Store<ST>::T*)pop, Q, g, ph, cd, cell0,
+                     nslab, bad);
+}
+
 hipError_t launch_init(int storage, void* pop, const double* Q, const Geom& g, const PhysD& ph, const Codec& cd,
-                       uint32_t cell0, uint32_t nslab, int* bad, hipStream_t s) {
-  const int block = 256;
-  const uint32_t nb = (nslab + block - 1) / block;
+                       uint32_t cell0, uint32_t nslab, int* bad, bool primitive, hipStream_t s) {
+  const uint32_t nb = (nslab + 255) / 256;
   if (nb == 0) return hipSuccess;
-  if (storage == 0)
-    hipLaunchKernelGGL(k_init<0>, dim3(nb), dim3(block), 0, s, (float*)pop, Q, g, ph, cd, cell0, nslab, bad);
-  else if (storage == 1)
-    hipLaunchKernelGGL(k_init<1>, dim3(nb), dim3(block), 0, s, (uint16_t*)pop, Q, g, ph, cd, cell0, nslab, bad);
-  else
-    hipLaunchKernelGGL(k_init<2>, dim3(nb), dim3(block), 0, s, (uint16_t*)pop, Q, g, ph, cd, cell0, nslab, bad);
+  if (storage == 0) (primitive ? init_t<0, true> : init_t<0, false>)(pop, Q, g, ph, cd, cell0, nslab, bad, nb, s);
+  else if (storage == 1) (primitive ? init_t<1, true> : init_t<1, false>)(pop, Q, g, ph, cd, cell0, nslab, bad, nb, s);
+  else (primitive ? init_t<2, true> : init_t<2, false>)(pop, Q, g, ph, cd, cell0, nslab, bad, nb, s);
   return hipGetLastError();
+}
+
+template <int ST, int BC>
+static hipError_t launch_primitives_t(const void* pop, double* out, const Geom& g, const Codec& cd, const PhysD& ph,
+                                      int parity, uint32_t cell0, uint32_t nslab, hipStream_t s) {
+  const uint32_t nb = (nslab + 255) / 256;
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_primitives<ST, BC>), dim3(nb), dim3(256), 0, s, (const typename Store<ST>::T*)pop, out, g, cd,
+                     ph, parity, cell0, nslab);
+  return hipGetLastError();
+}
+
+hipError_t launch_primitives(int storage, const void* pop, double* out, const Geom& g, const Codec& cd, const PhysD& ph,
+                             int parity, uint32_t cell0, uint32_t nslab, hipStream_t s) {
+#define CNSF_CASE(ST, BC) \
+  if (storage == ST && g.bc_x == BC) return launch_primitives_t<ST, BC>(pop, out, g, cd, ph, parity, cell0, nslab, s);
+  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2)
+  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2)
+  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2)
+#undef CNSF_CASE
+  return hipErrorInvalidValue;
 }
 
 template <int ST, int BC>

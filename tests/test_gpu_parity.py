@@ -241,6 +241,56 @@ def test_slab_set_state_and_moments():
     assert rel_l2(full, Qo) < 1e-6
 
 
+# ------------------------------------------------------------------ primitive fields
+def _primitive_fields(Q, prm):
+    rho, u, _, p, _ = lbm.primitives(Q, prm)
+    return np.concatenate([rho[None], u, p[None], Q[5:]], axis=0)
+
+
+@pytest.mark.parametrize("storage", [W.STORAGE_FP32, W.STORAGE_FP16])
+def test_set_primitive_equals_set_state(storage):
+    """The state set from (rho, u, p, tau, q) is the state set from the conserved
+    fields: the conversion runs in FP64 on both sides, so populations can differ
+    only where a last-bit FP64 difference flips their 32- or 16-bit rounding."""
+    cnsf = _cnsf()
+    case = W.random_case(13, 11, 9, seed=21, sensor=True, amp=0.5)
+    prm = dict(case.params, storage=storage)
+    La, Lb = cnsf.Lattice(prm), cnsf.Lattice(prm)
+    La.set_state(case.Q0)
+    Lb.set_primitive(_primitive_fields(case.Q0, prm))
+    for L in (La, Lb):
+        L.step(5)
+    Qa, Qb = La.moments(), Lb.moments()
+    d = float(np.max(np.abs(Qa - Qb)) / np.max(np.abs(Qa)))
+    log(f"case {case.name} storage {storage}: set_primitive vs set_state max rel diff {d:.2e}")
+    assert d < (1e-6 if storage == W.STORAGE_FP32 else 1e-3)
+
+
+def test_get_primitives_matches_oracle_conversion():
+    cnsf = _cnsf()
+    case = W.tgv(24)
+    L, Q = run_gpu(case, 7)
+    Pg = L.primitives()
+    rho, u, _, p, T = lbm.primitives(Q, case.params)
+    Po = np.concatenate([rho[None], u, p[None], T[None]], axis=0)
+    assert Pg.shape == (6,) + Q.shape[1:]
+    d = float(np.max(np.abs(Pg - Po) / np.maximum(np.abs(Po), 1e-3)))
+    log(f"case tgv24 primitives vs oracle conversion: max rel diff {d:.2e}")
+    assert d < 1e-13
+    assert np.array_equal(L.primitives(5, 3), Pg[:, 5:8])
+
+
+def test_set_primitive_rejects_negative_pressure():
+    cnsf = _cnsf()
+    case = W.random_case(8, 8, 8, seed=3)
+    P = _primitive_fields(case.Q0, case.params)
+    P[4, 2, 3, 4] = -0.1
+    L = cnsf.Lattice(case.params)
+    with pytest.raises(cnsf.CnsfError) as e:
+        L.set_primitive(P)
+    assert e.value.status == cnsf.CNSF_E_STATE
+
+
 # ------------------------------------------------------------------ shell spectrum
 def _spectrum_close(Eg, Eo):
     # FP64 on both sides; transforms round differently, so compare against
