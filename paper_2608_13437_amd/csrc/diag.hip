@@ -129,15 +129,17 @@ __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* _
 }
 
 // ------------------------------------------------------------------ spectral
-struct AxisGeom {
-  uint32_t n;        // line length
-  uint32_t stride;   // element stride along the line
+// One derivative pass: d_a u_c for every line along axis a.
+struct DerivAxis {
+  uint32_t n;               // line length
+  uint32_t stride;          // element stride along the line
   uint32_t nlines;
-  uint32_t lines_per_block;
-  uint32_t log2n;    // 0 if n is not a power of two
-  int axis;          // 0 x, 1 y, 2 z
-  int last;          // reduce eps into the partials
-  double kscale;     // 2 pi / (n dx)
+  uint32_t pairs_per_block; // line pairs held in LDS at once
+  uint32_t log2n;           // 0 if n is not a power of two
+  int axis;                 // 0 x, 1 y, 2 z
+  int init;                 // store into the accumulator instead of adding
+  double sign;
+  double kscale;            // 2 pi / (n dx)
 };
 
 __device__ inline uint32_t line_base(uint32_t l, int axis, const Geom& g) {
@@ -272,125 +274,116 @@ __device__ inline void fft_dif_inv(double2* buf, uint32_t n, uint32_t log2n, uin
   }
 }
 
-// Derivatives along one axis of u, v, w for a group of lines; accumulate into
-// div u and curl u:  omega_c = eps_{c a b} d_a u_b.
-__global__ void __launch_bounds__(DB) k_spectral_axis(double* __restrict__ fields, const Geom g, const AxisGeom ag,
-                                                      DiagPartial* __restrict__ partials) {
+// Spectral derivative along axis a of one velocity component, two adjacent
+// lines per complex transform: z = u_c(l) + i u_c(l+1).  The derivative
+// (multiply by i kappa, Nyquist mode to zero) is a real-linear map, so the
+// real and imaginary parts of D z are the derivatives of the two lines.  The
+// result times `sign` is stored into (init) or added to the accumulator, one
+// of div u, omega_x, omega_y, omega_z.  Powers of two use the LDS transform,
+// other lengths the spectral-derivative kernel as a direct sum.
+__global__ void __launch_bounds__(DB) k_deriv_axis(const double* __restrict__ uc, double* __restrict__ acc, const Geom g,
+                                                   const DerivAxis da) {
   extern __shared__ double2 lds[];
-  const uint32_t n = ag.n, TL = ag.lines_per_block;
-  const uint64_t N = g.ncells;
-  const double* u[3] = {fields, fields + N, fields + 2 * N};
-  const double* mu = fields + 3 * N;
-  double* divf = fields + 4 * N;
-  double* wf[3] = {fields + 5 * N, fields + 6 * N, fields + 7 * N};
-  const int a = ag.axis;
-  const int b1 = (a + 1) % 3, b2 = (a + 2) % 3;  // eps_{b2 a b1} = +1, eps_{b1 a b2} = -1
-  const bool pow2 = ag.log2n != 0;
-  const uint32_t np = lds_line(n);
-  double2* A = lds;             // u_a + i u_b1
-  double2* B = lds + TL * np;   // u_b2 + i 0
-  // direct path (non power of two): separate output rows and the derivative kernel
-  double2* Aout = pow2 ? A : lds + 2 * TL * np;
-  double2* Bout = pow2 ? B : lds + 3 * TL * np;
-  double2* tw = lds + 2 * TL * np;                       // power of two
-  double* Dk = (double*)(lds + 4 * TL * np);             // direct
-  if (pow2) fill_twiddles(tw, n);
-  if (!pow2) {
+  const uint32_t n = da.n, TP = da.pairs_per_block, np = lds_line(n);
+  const bool pow2 = da.log2n != 0;
+  double2* A = lds;
+  double2* Aout = pow2 ? A : lds + TP * np;
+  double2* tw = lds + TP * np;                      // power of two
+  double* Dk = (double*)(lds + 2 * TP * np);        // direct
+  if (pow2) {
+    fill_twiddles(tw, n);
+  } else {
     // D[m] = -(2/n) sum_{k=1}^{K} kappa_k sin(2 pi k m / n), Nyquist excluded
     const uint32_t K = (n % 2) ? (n - 1) / 2 : n / 2 - 1;
     for (uint32_t m = threadIdx.x; m < n; m += blockDim.x) {
       double sacc = 0.0;
       for (uint32_t k = 1; k <= K; ++k) sacc += (double)k * sinpi(2.0 * (double)((uint64_t)k * m % n) / (double)n);
-      Dk[m] = -2.0 / (double)n * ag.kscale * sacc;
+      Dk[m] = -2.0 / (double)n * da.kscale * sacc;
     }
   }
-  DiagPartial acc;
-  part_zero(acc);
-  const GroupRange gr = xcd_groups((ag.nlines + TL - 1) / TL);
+  const uint32_t npairs = (da.nlines + 1) / 2;
+  const GroupRange gr = xcd_groups((npairs + TP - 1) / TP);
   for (uint32_t grp = gr.begin; grp < gr.end; grp += gr.step) {
-    const uint32_t l0 = grp * TL;
-    const uint32_t cnt = min(TL, ag.nlines - l0);
+    const uint32_t p0 = grp * TP;
+    const uint32_t cnt = min(TP, npairs - p0);
     __syncthreads();
-    // load (bit-reversed positions for the decimation-in-time transform)
+    // load (bit-reversed positions for the decimation-in-time transform);
+    // along y and z, consecutive threads take consecutive line pairs
     for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
-      uint32_t line, j;
-      if (a == 0) { line = e / n; j = e % n; }
-      else { line = e % cnt; j = e / cnt; }
-      const uint32_t addr = line_base(l0 + line, a, g) + j * ag.stride;
-      const uint32_t pos = pow2 ? (__brev(j) >> (32 - ag.log2n)) : j;
-      A[line * np + lds_idx(pos)] = make_double2(u[a][addr], u[b1][addr]);
-      B[line * np + lds_idx(pos)] = make_double2(u[b2][addr], 0.0);
+      uint32_t pr, j;
+      if (da.axis == 0) { pr = e / n; j = e % n; }
+      else { pr = e % cnt; j = e / cnt; }
+      const uint32_t l0 = 2 * (p0 + pr);
+      const double x0 = uc[line_base(l0, da.axis, g) + j * da.stride];
+      const double x1 = l0 + 1 < da.nlines ? uc[line_base(l0 + 1, da.axis, g) + j * da.stride] : 0.0;
+      const uint32_t pos = pow2 ? (__brev(j) >> (32 - da.log2n)) : j;
+      A[pr * np + lds_idx(pos)] = make_double2(x0, x1);
     }
     __syncthreads();
     if (pow2) {
-      fft_dit(A, n, ag.log2n, cnt, tw);
-      fft_dit(B, n, ag.log2n, cnt, tw);
+      fft_dit(A, n, da.log2n, cnt, tw);
       // multiply by i kappa_j (Nyquist to zero) and 1/n for the inverse
       for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
-        const uint32_t j = e & (n - 1u), q = (e >> ag.log2n) * np + lds_idx(j);
+        const uint32_t j = e & (n - 1u), q = (e >> da.log2n) * np + lds_idx(j);
         double kj = (j < n / 2) ? (double)j : (j == n / 2 ? 0.0 : (double)j - (double)n);
-        kj *= ag.kscale / (double)n;
-        const double2 x = A[q], y = B[q];
+        kj *= da.kscale / (double)n;
+        const double2 x = A[q];
         A[q] = make_double2(-kj * x.y, kj * x.x);
-        B[q] = make_double2(-kj * y.y, kj * y.x);
       }
       __syncthreads();
-      fft_dif_inv(A, n, ag.log2n, cnt, tw);   // output in bit-reversed positions
-      fft_dif_inv(B, n, ag.log2n, cnt, tw);
+      fft_dif_inv(A, n, da.log2n, cnt, tw);   // output in bit-reversed positions
     } else {
-      // direct: d_j = sum_m D[m] x_{(j - m) mod n}
+      // direct: d_j = sum_m D[m] z_{(j - m) mod n}
       for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
-        const uint32_t line = e / n, j = e % n;
-        double da = 0.0, db1 = 0.0, db2 = 0.0;
+        const uint32_t pr = e / n, j = e % n;
+        double dr = 0.0, di = 0.0;
         for (uint32_t m = 0; m < n; ++m) {
-          const uint32_t src = line * np + lds_idx((j + n - m) % n);
+          const double2 z = A[pr * np + lds_idx((j + n - m) % n)];
           const double d = Dk[m];
-          da += d * A[src].x;
-          db1 += d * A[src].y;
-          db2 += d * B[src].x;
+          dr += d * z.x;
+          di += d * z.y;
         }
-        Aout[line * np + lds_idx(j)] = make_double2(da, db1);
-        Bout[line * np + lds_idx(j)] = make_double2(db2, 0.0);
+        Aout[pr * np + lds_idx(j)] = make_double2(dr, di);
       }
       __syncthreads();
     }
-    // write / accumulate
     for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
-      uint32_t line, j;
-      if (a == 0) { line = e / n; j = e % n; }
-      else { line = e % cnt; j = e / cnt; }
-      const uint32_t addr = line_base(l0 + line, a, g) + j * ag.stride;
-      const uint32_t pos = pow2 ? (__brev(j) >> (32 - ag.log2n)) : j;
-      const double2 ra = Aout[line * np + lds_idx(pos)];
-      const double dua = ra.x, dub1 = ra.y, dub2 = Bout[line * np + lds_idx(pos)].x;
-      // omega_{b2} += d_a u_{b1};  omega_{b1} -= d_a u_{b2}
-      double dv = dua;
-      const double wb2 = dub1, wb1 = -dub2;
-      if (a == 0) {        // first pass: div, omega_z (b2 = 2), omega_y (b1 = 1)
-        divf[addr] = dv;
-        wf[b2][addr] = wb2;
-        wf[b1][addr] = wb1;
-      } else if (a == 1) { // omega_x (b2 = 0) starts here; omega_z (b1 = 2) accumulates
-        divf[addr] += dv;
-        wf[b2][addr] = wb2;
-        wf[b1][addr] += wb1;
-      } else {             // last pass: b1 = 0 (omega_x), b2 = 1 (omega_y); reduce
-        dv += divf[addr];
-        const double wx = wf[0][addr] + wb1;
-        const double wy = wf[1][addr] + wb2;
-        const double wz = wf[2][addr];
-        const double m = mu[addr];
-        acc.eps_s += m * (wx * wx + wy * wy + wz * wz);
-        acc.eps_d += m * dv * dv;
+      uint32_t pr, j;
+      if (da.axis == 0) { pr = e / n; j = e % n; }
+      else { pr = e % cnt; j = e / cnt; }
+      const uint32_t l0 = 2 * (p0 + pr);
+      const uint32_t pos = pow2 ? (__brev(j) >> (32 - da.log2n)) : j;
+      const double2 r = Aout[pr * np + lds_idx(pos)];
+      const uint32_t a0 = line_base(l0, da.axis, g) + j * da.stride;
+      acc[a0] = da.init ? da.sign * r.x : acc[a0] + da.sign * r.x;
+      if (l0 + 1 < da.nlines) {
+        const uint32_t a1 = line_base(l0 + 1, da.axis, g) + j * da.stride;
+        acc[a1] = da.init ? da.sign * r.y : acc[a1] + da.sign * r.y;
       }
     }
   }
-  if (ag.last) {
-    DiagPartial tot = block_reduce(acc);
-    if (threadIdx.x == 0) {
-      partials[blockIdx.x].eps_s = tot.eps_s;
-      partials[blockIdx.x].eps_d = tot.eps_d;
-    }
+}
+
+// eps sums: sum of mu |omega|^2 and mu (div u)^2 over the cells, per block.
+__global__ void __launch_bounds__(DB) k_eps_sums(const double* __restrict__ fields, const Geom g,
+                                                 DiagPartial* __restrict__ partials) {
+  const uint64_t N = g.ncells;
+  const double* mu = fields + 3 * N;
+  const double* divf = fields + 4 * N;
+  const double* wx = fields + 5 * N;
+  const double* wy = fields + 6 * N;
+  const double* wz = fields + 7 * N;
+  DiagPartial acc;
+  part_zero(acc);
+  for (uint32_t c = blockIdx.x * DB + threadIdx.x; c < g.ncells; c += gridDim.x * DB) {
+    const double m = mu[c], d = divf[c], x = wx[c], y = wy[c], z = wz[c];
+    acc.eps_s += m * (x * x + y * y + z * z);
+    acc.eps_d += m * d * d;
+  }
+  DiagPartial tot = block_reduce(acc);
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x].eps_s = tot.eps_s;
+    partials[blockIdx.x].eps_d = tot.eps_d;
   }
 }
 
@@ -553,32 +546,45 @@ hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const P
   return hipErrorInvalidValue;
 }
 
+// Nine derivative passes d_a u_c into div u = sum_a d_a u_a and
+// omega_b = eps_{b a c} d_a u_c, then the eps sums.  The first pass into each
+// accumulator stores, the later ones add.
 hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial* partials, hipStream_t s) {
   const uint32_t dims[3] = {g.nx, g.ny, g.nz};
   const uint32_t strides[3] = {1u, g.nx, g.nxy};
-  for (int a = 0; a < 3; ++a) {
-    AxisGeom ag{};
-    ag.n = dims[a];
-    ag.stride = strides[a];
-    ag.nlines = g.ncells / dims[a];
+  const uint64_t N = g.ncells;
+  // (axis a, component c, accumulator 0 div / 1 + b omega_b, sign, init)
+  struct Pass { int a, c, target; double sign; int init; };
+  const Pass passes[9] = {
+      {0, 0, 0, 1.0, 1}, {0, 1, 3, 1.0, 1}, {0, 2, 2, -1.0, 1},   // div; omega_z += d_x v; omega_y -= d_x w
+      {1, 0, 3, -1.0, 0}, {1, 1, 0, 1.0, 0}, {1, 2, 1, 1.0, 1},   // omega_z -= d_y u; div; omega_x += d_y w
+      {2, 0, 2, 1.0, 0}, {2, 1, 1, -1.0, 0}, {2, 2, 0, 1.0, 0}};  // omega_y += d_z u; omega_x -= d_z v; div
+  for (const Pass& ps : passes) {
+    DerivAxis da{};
+    da.n = dims[ps.a];
+    da.stride = strides[ps.a];
+    da.nlines = (uint32_t)(N / da.n);
     uint32_t lg = 0;
-    while ((1u << lg) < ag.n) ++lg;
-    ag.log2n = ((1u << lg) == ag.n && ag.n >= 2) ? lg : 0;
-    // LDS: 2 (FFT) or 4 (direct) complex rows per line, plus the twiddle
-    // table (FFT) or the derivative kernel (direct), <= 64 KiB
-    const uint32_t rows = ag.log2n ? 2u : 4u;
-    const uint32_t extra = ag.log2n ? (ag.n - 1) * 16u : (ag.n + 2) * 8u;
-    uint32_t tl = (65536u - extra) / (rows * lds_line(ag.n) * 16u);
-    ag.lines_per_block = tl < 1 ? 1 : (tl > 16 ? 16 : tl);
-    ag.axis = a;
-    ag.last = (a == 2);
-    ag.kscale = 2.0 * M_PI / ((double)ag.n * dx);
-    const size_t lds = (size_t)rows * ag.lines_per_block * lds_line(ag.n) * sizeof(double2) + extra;
-    hipLaunchKernelGGL(k_spectral_axis, dim3(DIAG_BLOCKS), dim3(DB), lds, s, fields, g, ag, partials);
+    while ((1u << lg) < da.n) ++lg;
+    da.log2n = ((1u << lg) == da.n && da.n >= 2) ? lg : 0;
+    // LDS: one (FFT) or two (direct) complex rows per line pair, plus the
+    // twiddle table (FFT) or the derivative kernel (direct), <= 64 KiB
+    const uint32_t rows = da.log2n ? 1u : 2u;
+    const uint32_t extra = da.log2n ? (da.n - 1) * 16u : (da.n + 2) * 8u;
+    uint32_t tp = (65536u - extra) / (rows * lds_line(da.n) * 16u);
+    da.pairs_per_block = tp < 1 ? 1 : (tp > 16 ? 16 : tp);
+    da.axis = ps.a;
+    da.init = ps.init;
+    da.sign = ps.sign;
+    da.kscale = 2.0 * M_PI / ((double)da.n * dx);
+    const size_t lds = (size_t)rows * da.pairs_per_block * lds_line(da.n) * sizeof(double2) + extra;
+    hipLaunchKernelGGL(k_deriv_axis, dim3(DIAG_BLOCKS), dim3(DB), lds, s, fields + ps.c * N,
+                       fields + (4 + ps.target) * N, g, da);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  hipLaunchKernelGGL(k_eps_sums, dim3(DIAG_BLOCKS), dim3(DB), 0, s, fields, g, partials);
+  return hipGetLastError();
 }
 
 uint32_t spectrum_shells(uint32_t n) {
