@@ -139,6 +139,8 @@ int cnsf_required_bytes(const cnsf_params* p, size_t* bytes);
  *           256-byte aligned; never freed by the library.  NULL: the library
  *           allocates (hipMalloc) and frees it in cnsf_destroy.
  *  stream   hipStream_t on which all work is enqueued (NULL: default stream).
+ * The whole array is cleared on the stream (the unused slots past the last
+ * cell too, so exported checkpoints of equal states are byte-identical).
  * Errors: CNSF_E_INVALID (any range listed under cnsf_params, omega outside
  * (0,2), unknown enum, sub-characteristic bound), CNSF_E_NOMEM, CNSF_E_DEVICE. */
 int cnsf_create(const cnsf_params* p, void* dev_buf, size_t bytes, void* stream, cnsf_lattice** out);
@@ -193,6 +195,15 @@ int cnsf_diagnostics(cnsf_lattice* lat, int32_t flags, cnsf_diag* out);
 int cnsf_spectrum_shells(const cnsf_lattice* lat, int32_t* nshells);
 int cnsf_spectrum(cnsf_lattice* lat, double* E, int32_t nshells, int32_t where);
 
+/* Advance n >= 1 steps and return the FP64 diagnostics of the time level at
+ * entry, the values cnsf_diagnostics(lat, flags, out) would have returned
+ * before the call (sums to rounding order; minima and counts exactly).  The
+ * first update reads that level anyway: it also forms the sums and writes the
+ * velocity fields the spectral derivatives need, so the populations are read
+ * once instead of twice.  Returns when the n steps are done (synchronises the
+ * stream).  Errors as cnsf_step and cnsf_diagnostics. */
+int cnsf_step_diagnostics(cnsf_lattice* lat, int64_t n, int32_t flags, cnsf_diag* out);
+
 /* Step counter, parity and the byte size of an exported checkpoint. */
 int cnsf_get_info(const cnsf_lattice* lat, int64_t* step, int32_t* parity, size_t* checkpoint_bytes);
 
@@ -227,8 +238,8 @@ const char* cnsf_status_string(int status);
  */
 typedef struct cnsf_batch cnsf_batch;
 
-/* Create a batch of n members.  dev_buf / bytes as in cnsf_create, sized by
- * cnsf_batch_required_bytes (NULL: library-allocated). */
+/* Create a batch of n members.  dev_buf / bytes as in cnsf_create (cleared the
+ * same way), sized by cnsf_batch_required_bytes (NULL: library-allocated). */
 int cnsf_batch_required_bytes(const cnsf_params* members, int32_t n, size_t* bytes);
 int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size_t bytes, void* stream,
                       cnsf_batch** out);

@@ -87,6 +87,7 @@ def library():
             "cnsf_set_primitive": [vp, dp, i32, i32, i32],
             "cnsf_get_primitives": [vp, dp, i32, i32, i32],
             "cnsf_diagnostics": [vp, i32, C.POINTER(cnsf_diag)],
+            "cnsf_step_diagnostics": [vp, i64, i32, C.POINTER(cnsf_diag)],
             "cnsf_spectrum_shells": [vp, C.POINTER(i32)],
             "cnsf_spectrum": [vp, dp, i32, i32],
             "cnsf_get_info": [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(sz)],
@@ -154,6 +155,18 @@ def cnsf_step(h, n: int):
 
 def cnsf_get_moments(h, out_ptr: int, z0: int, nzs: int, where: int):
     _check(library().cnsf_get_moments(h, C.cast(C.c_void_p(out_ptr), C.POINTER(C.c_double)), z0, nzs, where))
+
+
+def _diag_dict(d: cnsf_diag) -> dict:
+    return dict(step=d.step, time=d.time, mass=d.mass, momentum=list(d.momentum), energy=d.energy,
+                E_k=d.E_k, eps_s=d.eps_s, eps_d=d.eps_d, min_rho=d.min_rho, min_p=d.min_p,
+                sensor_fraction=d.sensor_fraction, nonfinite=d.nonfinite)
+
+
+def cnsf_step_diagnostics(h, n: int, flags: int) -> cnsf_diag:
+    d = cnsf_diag()
+    _check(library().cnsf_step_diagnostics(h, n, flags, C.byref(d)))
+    return d
 
 
 def cnsf_set_primitive(h, P_ptr: int, z0: int, nzs: int, where: int):
@@ -324,9 +337,11 @@ class Lattice:
 
     def diagnostics(self, spectral: bool = True) -> dict:
         d = cnsf_diagnostics(self.h, CNSF_DIAG_SPECTRAL if spectral else CNSF_DIAG_SUMS)
-        return dict(step=d.step, time=d.time, mass=d.mass, momentum=list(d.momentum), energy=d.energy,
-                    E_k=d.E_k, eps_s=d.eps_s, eps_d=d.eps_d, min_rho=d.min_rho, min_p=d.min_p,
-                    sensor_fraction=d.sensor_fraction, nonfinite=d.nonfinite)
+        return _diag_dict(d)
+
+    def step_diagnostics(self, n: int, spectral: bool = True) -> dict:
+        """Advance n steps; return the diagnostics of the level at entry (one population read)."""
+        return _diag_dict(cnsf_step_diagnostics(self.h, int(n), CNSF_DIAG_SPECTRAL if spectral else CNSF_DIAG_SUMS))
 
     def spectrum(self, device: bool = False):
         """Shell-averaged velocity spectrum E[k], k = 0 .. 1 + nint(sqrt(3) n / 2) - 1 (FP64)."""

@@ -231,6 +231,9 @@ struct cnsf_lattice {
   DiagPartial* dresult = nullptr;
   double* fields = nullptr;           // spectral workspace (8 doubles per cell)
   double* spec = nullptr;             // shell-spectrum partials and output
+  DiagPartial* step_partials = nullptr;  // per-block sums of the fused diagnostic step
+  uint32_t step_partials_cap = 0;
+  DiagPartial* dresult2 = nullptr;       // eps sums of the fused diagnostic step
 };
 
 extern "C" {
@@ -297,6 +300,13 @@ int cnsf_create(const cnsf_params* p, void* dev_buf, size_t bytes, void* stream,
     cnsf_destroy(L);
     return fail(CNSF_E_NOMEM, "hipMalloc of small buffers: %s", hipGetErrorString(e));
   }
+  // the slots past the last cell of the final group are never written by a
+  // step; cleared here, equal states export byte-identical checkpoints
+  e = hipMemsetAsync(L->pop, 0, need, L->stream);
+  if (e != hipSuccess) {
+    cnsf_destroy(L);
+    return hip_fail(e, "clearing the population array");
+  }
   *out = L;
   return CNSF_OK;
 }
@@ -312,6 +322,8 @@ int cnsf_destroy(cnsf_lattice* L) {
   if (L->dresult) (void)hipFree(L->dresult);
   if (L->fields) (void)hipFree(L->fields);
   if (L->spec) (void)hipFree(L->spec);
+  if (L->step_partials) (void)hipFree(L->step_partials);
+  if (L->dresult2) (void)hipFree(L->dresult2);
   delete L;
   return CNSF_OK;
 }
@@ -431,6 +443,24 @@ int cnsf_get_moments(cnsf_lattice* L, double* out, int32_t z0, int32_t nzs, int3
   return CNSF_OK;
 }
 
+static void fill_diag(const cnsf_lattice* L, const DiagPartial& r, bool spectral, int64_t step, cnsf_diag* d) {
+  const double n = (double)L->g.ncells;
+  d->step = step;
+  d->time = (double)step * L->p.dt;
+  d->mass = r.mass;
+  d->momentum[0] = r.mx;
+  d->momentum[1] = r.my;
+  d->momentum[2] = r.mz;
+  d->energy = r.energy;
+  d->E_k = 0.5 * r.ek2 / n;
+  d->eps_s = spectral ? r.eps_s / n : 0.0;
+  d->eps_d = spectral ? 4.0 / 3.0 * r.eps_d / n : 0.0;
+  d->min_rho = r.min_rho;
+  d->min_p = r.min_p;
+  d->sensor_fraction = r.sensor / n;
+  d->nonfinite = (int64_t)r.nonfinite;
+}
+
 int cnsf_diagnostics(cnsf_lattice* L, int32_t flags, cnsf_diag* d) {
   if (!L || !d) return fail(CNSF_E_INVALID, "NULL argument");
   (void)hipSetDevice(L->device);
@@ -445,27 +475,68 @@ int cnsf_diagnostics(cnsf_lattice* L, int32_t flags, cnsf_diag* d) {
   }
   e = launch_diag_sums(L->p.storage, L->pop, L->g, L->ph, L->phd, L->cd, L->parity, L->partials,
                        spectral ? L->fields : nullptr, L->stream);
-  if (e == hipSuccess && spectral) e = launch_spectral(L->g, L->p.dx, L->fields, L->partials, L->stream);
+  if (e == hipSuccess && spectral) e = launch_spectral(L->g, L->p.dx, L->fields, L->partials, false, L->stream);
   if (e == hipSuccess) e = launch_diag_final(L->partials, DIAG_BLOCKS, L->dresult, L->stream);
   DiagPartial r{};
   if (e == hipSuccess) e = hipMemcpyAsync(&r, L->dresult, sizeof r, hipMemcpyDeviceToHost, L->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostics");
-  const double n = (double)L->g.ncells;
-  d->step = L->step;
-  d->time = (double)L->step * L->p.dt;
-  d->mass = r.mass;
-  d->momentum[0] = r.mx;
-  d->momentum[1] = r.my;
-  d->momentum[2] = r.mz;
-  d->energy = r.energy;
-  d->E_k = 0.5 * r.ek2 / n;
-  d->eps_s = spectral ? r.eps_s / n : 0.0;
-  d->eps_d = spectral ? 4.0 / 3.0 * r.eps_d / n : 0.0;
-  d->min_rho = r.min_rho;
-  d->min_p = r.min_p;
-  d->sensor_fraction = r.sensor / n;
-  d->nonfinite = (int64_t)r.nonfinite;
+  fill_diag(L, r, spectral, L->step, d);
+  return CNSF_OK;
+}
+
+int cnsf_step_diagnostics(cnsf_lattice* L, int64_t n, int32_t flags, cnsf_diag* d) {
+  if (!L || !d) return fail(CNSF_E_INVALID, "NULL argument");
+  if (n < 1) return fail(CNSF_E_INVALID, "n = %lld < 1", (long long)n);
+  (void)hipSetDevice(L->device);
+  const bool spectral = (flags & CNSF_DIAG_SPECTRAL) && L->g.bc_x == CNSF_BC_PERIODIC;
+  hipError_t e = hipSuccess;
+  if (spectral && !L->fields) {
+    e = hipMalloc(&L->fields, (size_t)8 * L->g.ncells * sizeof(double));
+    if (e != hipSuccess) {
+      L->fields = nullptr;
+      return fail(CNSF_E_NOMEM, "spectral workspace: %s", hipGetErrorString(e));
+    }
+  }
+  const uint32_t nb = update_blocks(L->g, L->lc);
+  if (L->step_partials_cap < nb) {
+    if (L->step_partials) (void)hipFree(L->step_partials);
+    L->step_partials = nullptr;
+    L->step_partials_cap = 0;
+    e = hipMalloc(&L->step_partials, (size_t)nb * sizeof(DiagPartial));
+    if (e != hipSuccess) {
+      L->step_partials = nullptr;
+      return fail(CNSF_E_NOMEM, "step partials: %s", hipGetErrorString(e));
+    }
+    L->step_partials_cap = nb;
+  }
+  if (!L->dresult2) {
+    e = hipMalloc(&L->dresult2, sizeof(DiagPartial));
+    if (e != hipSuccess) {
+      L->dresult2 = nullptr;
+      return fail(CNSF_E_NOMEM, "diagnostic result: %s", hipGetErrorString(e));
+    }
+  }
+  const int64_t step0 = L->step;
+  // the first update reduces the sums of the level it reads and writes u, v, w, mu
+  e = launch_update_diag(L->p.storage, L->pop, L->g, L->ph, L->cd, L->parity, L->lc, L->phd, L->step_partials,
+                         spectral ? L->fields : nullptr, L->stream);
+  if (e != hipSuccess) return hip_fail(e, "fused diagnostic update");
+  L->parity ^= 1;
+  ++L->step;
+  if (spectral) e = launch_spectral(L->g, L->p.dx, L->fields, L->partials, true, L->stream);
+  if (e == hipSuccess) e = launch_diag_final(L->step_partials, (int)nb, L->dresult, L->stream);
+  if (e == hipSuccess && spectral) e = launch_diag_final(L->partials, DIAG_BLOCKS, L->dresult2, L->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostic reductions");
+  if (int r = cnsf_step(L, n - 1)) return r;
+  DiagPartial r{}, r2{};
+  e = hipMemcpyAsync(&r, L->dresult, sizeof r, hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess && spectral) e = hipMemcpyAsync(&r2, L->dresult2, sizeof r2, hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "step_diagnostics");
+  r.eps_s = r2.eps_s;
+  r.eps_d = r2.eps_d;
+  fill_diag(L, r, spectral, step0, d);
   return CNSF_OK;
 }
 

@@ -218,6 +218,12 @@ int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size
     cnsf_batch_destroy(b);
     return r;
   }
+  // padding slots are never written by a step; cleared, exports are deterministic
+  e = hipMemsetAsync(b->base, 0, need, b->stream);
+  if (e != hipSuccess) {
+    cnsf_batch_destroy(b);
+    return hip_fail(e, "clearing the population array");
+  }
   *out = b;
   return CNSF_OK;
 }

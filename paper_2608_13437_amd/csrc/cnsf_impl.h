@@ -319,10 +319,10 @@ __device__ inline void collide_dev(float g[NV], const float dQ[NC], const float 
 }
 
 // The whole cell update on shifted populations (FP32).
-__device__ inline void update_cell(float g[NC][NV], const Codec& cd, const Phys& ph) {
+__device__ inline void update_cell(float g[NC][NV], const Codec& cd, const Phys& ph, float* chi_out = nullptr) {
   float dQ[NC], Q[NC];
   DevPrim P;
-  const float omega = cell_state(g, cd, ph, dQ, Q, P);
+  const float omega = cell_state(g, cd, ph, dQ, Q, P, chi_out);
   collide_dev<0>(g[0], dQ, Q, P, ph, omega);
   collide_dev<1>(g[1], dQ, Q, P, ph, omega);
   collide_dev<2>(g[2], dQ, Q, P, ph, omega);

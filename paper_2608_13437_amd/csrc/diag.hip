@@ -14,67 +14,12 @@
 #include <cmath>
 
 #include "cnsf_impl.h"
+#include "diag_common.h"
 #include "launch.h"
 
 namespace cnsf {
 
 constexpr int DB = 256;  // threads per diagnostics block
-
-__device__ inline void part_zero(DiagPartial& p) {
-  p.mass = p.mx = p.my = p.mz = p.energy = p.ek2 = 0.0;
-  p.min_rho = p.min_p = 1e300;
-  p.sensor = p.nonfinite = 0.0;
-  p.eps_s = p.eps_d = 0.0;
-}
-
-__device__ inline void part_add(DiagPartial& a, const DiagPartial& b) {
-  a.mass += b.mass;
-  a.mx += b.mx;
-  a.my += b.my;
-  a.mz += b.mz;
-  a.energy += b.energy;
-  a.ek2 += b.ek2;
-  a.min_rho = fmin(a.min_rho, b.min_rho);
-  a.min_p = fmin(a.min_p, b.min_p);
-  a.sensor += b.sensor;
-  a.nonfinite += b.nonfinite;
-  a.eps_s += b.eps_s;
-  a.eps_d += b.eps_d;
-}
-
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
-}
-__device__ inline double wave_min(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_down(v, o, 64));
-  return v;
-}
-
-// Block total of one DiagPartial per thread (wave shuffles, then the DB/64
-// wave results in index order); valid in thread 0.  Deterministic.
-__device__ inline DiagPartial block_reduce(DiagPartial v) {
-  __shared__ DiagPartial sh[DB / 64];
-  v.mass = wave_sum(v.mass);
-  v.mx = wave_sum(v.mx);
-  v.my = wave_sum(v.my);
-  v.mz = wave_sum(v.mz);
-  v.energy = wave_sum(v.energy);
-  v.ek2 = wave_sum(v.ek2);
-  v.min_rho = wave_min(v.min_rho);
-  v.min_p = wave_min(v.min_p);
-  v.sensor = wave_sum(v.sensor);
-  v.nonfinite = wave_sum(v.nonfinite);
-  v.eps_s = wave_sum(v.eps_s);
-  v.eps_d = wave_sum(v.eps_d);
-  const int w = threadIdx.x / 64;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) sh[w] = v;
-  __syncthreads();
-  DiagPartial t = sh[0];
-  for (int i = 1; i < DB / 64; ++i) part_add(t, sh[i]);
-  return t;
-}
 
 template <int ST, int BC>
 __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* __restrict__ pop, const Geom g,
@@ -90,39 +35,13 @@ __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* _
     // the stored values are FP32 or 16-bit: gather them in FP32 (exact), sum in FP64
     float gf[NC][NV];
     gather<ST, BC, true, float>(pop, g, cd, n, parity, off, gf);
-    double Q[NC];
-    bool finite = true;
-#pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int i = 0; i < NV; ++i) s += (double)gf[k][i];
-      Q[k] = q_ref<double>(cd, k) + s;
-      finite = finite && isfinite(s);
-    }
-    Prim<double> P = primitives<double>(Q, phd);
-    acc.mass += Q[0];
-    acc.mx += Q[1];
-    acc.my += Q[2];
-    acc.mz += Q[3];
-    acc.energy += Q[4];
-    acc.ek2 += Q[1] * P.u[0] + Q[2] * P.u[1] + Q[3] * P.u[2];
-    acc.min_rho = fmin(acc.min_rho, P.rho);
-    acc.min_p = fmin(acc.min_p, P.p);
-    acc.nonfinite += finite ? 0.0 : 1.0;
+    cell_sums(gf, cd, phd, c, g.ncells, fields, acc);
     // the sensor decision as the FP32 update takes it
     float dQf[NC], Qf[NC];
     DevPrim Pf;
     float chi = 0.0f;
     cell_state(gf, cd, ph, dQf, Qf, Pf, &chi);
     acc.sensor += chi > 0.0f ? 1.0 : 0.0;
-    if (fields) {
-      const uint64_t N = g.ncells;
-      fields[c] = P.u[0];
-      fields[N + c] = P.u[1];
-      fields[2 * N + c] = P.u[2];
-      fields[3 * N + c] = P.muT;
-    }
   }
   DiagPartial tot = block_reduce(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -364,9 +283,11 @@ __global__ void __launch_bounds__(DB) k_deriv_axis(const double* __restrict__ uc
   }
 }
 
-// eps sums: sum of mu |omega|^2 and mu (div u)^2 over the cells, per block.
+// eps sums: sum of mu |omega|^2 and mu (div u)^2 over the cells, per block,
+// into the eps fields of the block's partial (full: a whole partial, the
+// other fields neutral).
 __global__ void __launch_bounds__(DB) k_eps_sums(const double* __restrict__ fields, const Geom g,
-                                                 DiagPartial* __restrict__ partials) {
+                                                 DiagPartial* __restrict__ partials, int full) {
   const uint64_t N = g.ncells;
   const double* mu = fields + 3 * N;
   const double* divf = fields + 4 * N;
@@ -382,8 +303,12 @@ __global__ void __launch_bounds__(DB) k_eps_sums(const double* __restrict__ fiel
   }
   DiagPartial tot = block_reduce(acc);
   if (threadIdx.x == 0) {
-    partials[blockIdx.x].eps_s = tot.eps_s;
-    partials[blockIdx.x].eps_d = tot.eps_d;
+    if (full) {
+      partials[blockIdx.x] = tot;
+    } else {
+      partials[blockIdx.x].eps_s = tot.eps_s;
+      partials[blockIdx.x].eps_d = tot.eps_d;
+    }
   }
 }
 
@@ -549,7 +474,8 @@ hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const P
 // Nine derivative passes d_a u_c into div u = sum_a d_a u_a and
 // omega_b = eps_{b a c} d_a u_c, then the eps sums.  The first pass into each
 // accumulator stores, the later ones add.
-hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial* partials, hipStream_t s) {
+hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial* partials, bool full,
+                           hipStream_t s) {
   const uint32_t dims[3] = {g.nx, g.ny, g.nz};
   const uint32_t strides[3] = {1u, g.nx, g.nxy};
   const uint64_t N = g.ncells;
@@ -583,7 +509,7 @@ hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_eps_sums, dim3(DIAG_BLOCKS), dim3(DB), 0, s, fields, g, partials);
+  hipLaunchKernelGGL(k_eps_sums, dim3(DIAG_BLOCKS), dim3(DB), 0, s, fields, g, partials, full ? 1 : 0);
   return hipGetLastError();
 }
 

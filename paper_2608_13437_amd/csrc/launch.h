@@ -37,10 +37,20 @@ struct DiagPartial {
   double eps_s, eps_d;                   // sums of mu |curl u|^2 and mu (div u)^2
 };
 constexpr int DIAG_BLOCKS = 2048;
+// The update of one time level that also reduces that level's Eq. (7) sums:
+// one DiagPartial per block (update_blocks of them) and, if fields is given,
+// u, v, w, mu into fields.
+uint32_t update_blocks(const Geom& g, const Launch& lc);
+hipError_t launch_update_diag(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
+                              const Launch& lc, const PhysD& phd, DiagPartial* partials, double* fields,
+                              hipStream_t s);
 hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const Phys& ph, const PhysD& phd,
                             const Codec& cd, int parity, DiagPartial* partials, double* fields, hipStream_t s);
 // fields: u, v, w, mu (4 * ncells doubles), then div, wx, wy, wz (4 * ncells).
-hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial* partials, hipStream_t s);
+// Spectral eps sums of the u, v, w, mu fields into DIAG_BLOCKS partials: only
+// their eps fields, or (full) whole partials with the other fields neutral.
+hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial* partials, bool full,
+                           hipStream_t s);
 hipError_t launch_diag_final(DiagPartial* partials, int nparts, DiagPartial* out, hipStream_t s);
 // Shell spectrum of the velocity held in fields (u, v, w: the first 3 * ncells
 // doubles, written by launch_diag_sums); uses fields[4 ncells, 7 ncells) as

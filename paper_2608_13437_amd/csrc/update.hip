@@ -8,6 +8,7 @@
 // pass (read from and write to the six face neighbours), so one array holds
 // the whole lattice.
 #include "cnsf_impl.h"
+#include "diag_common.h"
 #include "launch.h"
 
 namespace cnsf {
@@ -28,10 +29,18 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb) {
 // of 8) the blocks of XCD j stride over the j-th eighth of the tiles, so
 // neighbouring tiles, which share the +-x halo lines of the odd pass, are in
 // flight in the same L2.  Without the remap the blocks stride over all tiles.
-template <int ST, int BC, bool SC, int PAR>
+//
+// DIAG instances also reduce the Eq. (7) sums of the time level they read
+// (one partial per block, as the diagnostics readout forms them) and, when
+// `fields` is given, write u, v, w, mu for the spectral derivatives.
+template <int ST, int BC, bool SC, int PAR, bool DIAG>
 __global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restrict__ pop, const Geom g, const Phys ph,
-                                                const Codec cd, uint32_t tile, uint32_t ntiles, int remap) {
+                                                const Codec cd, uint32_t tile, uint32_t ntiles, int remap,
+                                                const PhysD phd, DiagPartial* __restrict__ partials,
+                                                double* __restrict__ fields) {
   constexpr int parity = PAR;
+  DiagPartial acc;
+  if constexpr (DIAG) part_zero(acc);
   uint32_t t_begin = blockIdx.x, t_step = gridDim.x, t_end = ntiles;
   if (remap && gridDim.x >= ntiles) {
     t_begin = xcd_block(blockIdx.x, ntiles);
@@ -52,9 +61,20 @@ __global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restric
       stream_offsets<ST, BC>(g, n, parity, off);
       float gv[NC][NV];
       gather<ST, BC, SC, float>(pop, g, cd, n, parity, off, gv);
-      update_cell(gv, cd, ph);
+      if constexpr (DIAG) {
+        cell_sums(gv, cd, phd, c, g.ncells, fields, acc);
+        float chi = 0.0f;
+        update_cell(gv, cd, ph, &chi);
+        acc.sensor += chi > 0.0f ? 1.0 : 0.0;
+      } else {
+        update_cell(gv, cd, ph);
+      }
       scatter<ST, BC, SC>(pop, g, cd, n, parity, off, gv);
     }
+  }
+  if constexpr (DIAG) {
+    const DiagPartial tot = block_reduce(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
   }
 }
 
@@ -154,26 +174,50 @@ __global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uin
 }
 
 // ------------------------------------------------------------------ launchers
-template <int ST, int BC, bool SC>
-static hipError_t launch_update_t(void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
-                                  const Launch& lc, hipStream_t s) {
+uint32_t update_blocks(const Geom& g, const Launch& lc) {
   const uint32_t ntiles = (g.ncells + lc.tile - 1) / lc.tile;
-  const uint32_t nb = (lc.grid > 0 && (uint32_t)lc.grid < ntiles) ? (uint32_t)lc.grid : ntiles;
+  return (lc.grid > 0 && (uint32_t)lc.grid < ntiles) ? (uint32_t)lc.grid : ntiles;
+}
+
+template <int ST, int BC, bool SC, bool DIAG>
+static hipError_t launch_update_t(void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
+                                  const Launch& lc, const PhysD& phd, DiagPartial* partials, double* fields,
+                                  hipStream_t s) {
+  const uint32_t ntiles = (g.ncells + lc.tile - 1) / lc.tile;
+  const uint32_t nb = update_blocks(g, lc);
   using T = typename Store<ST>::T;
   if (parity)
-    hipLaunchKernelGGL((k_update<ST, BC, SC, 1>), dim3(nb), dim3(lc.block), 0, s, (T*)pop, g, ph, cd,
-                       (uint32_t)lc.tile, ntiles, lc.remap);
+    hipLaunchKernelGGL((k_update<ST, BC, SC, 1, DIAG>), dim3(nb), dim3(lc.block), 0, s, (T*)pop, g, ph, cd,
+                       (uint32_t)lc.tile, ntiles, lc.remap, phd, partials, fields);
   else
-    hipLaunchKernelGGL((k_update<ST, BC, SC, 0>), dim3(nb), dim3(lc.block), 0, s, (T*)pop, g, ph, cd,
-                       (uint32_t)lc.tile, ntiles, lc.remap);
+    hipLaunchKernelGGL((k_update<ST, BC, SC, 0, DIAG>), dim3(nb), dim3(lc.block), 0, s, (T*)pop, g, ph, cd,
+                       (uint32_t)lc.tile, ntiles, lc.remap, phd, partials, fields);
   return hipGetLastError();
 }
 
 hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
                          const Launch& lc, hipStream_t s) {
   const bool sc = cd.scaled != 0;
-#define CNSF_CASE(ST, BC, SC) \
-  if (storage == ST && g.bc_x == BC && sc == SC) return launch_update_t<ST, BC, SC>(pop, g, ph, cd, parity, lc, s);
+  const PhysD none{};
+#define CNSF_CASE(ST, BC, SC)                              \
+  if (storage == ST && g.bc_x == BC && sc == SC)           \
+    return launch_update_t<ST, BC, SC, false>(pop, g, ph, cd, parity, lc, none, nullptr, nullptr, s);
+  CNSF_CASE(0, 0, false) CNSF_CASE(0, 1, false) CNSF_CASE(0, 2, false)
+  CNSF_CASE(1, 0, false) CNSF_CASE(1, 1, false) CNSF_CASE(1, 2, false)
+  CNSF_CASE(2, 0, false) CNSF_CASE(2, 1, false) CNSF_CASE(2, 2, false)
+  CNSF_CASE(1, 0, true) CNSF_CASE(1, 1, true) CNSF_CASE(1, 2, true)
+  CNSF_CASE(2, 0, true) CNSF_CASE(2, 1, true) CNSF_CASE(2, 2, true)
+#undef CNSF_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_update_diag(int storage, void* pop, const Geom& g, const Phys& ph, const Codec& cd, int parity,
+                              const Launch& lc, const PhysD& phd, DiagPartial* partials, double* fields,
+                              hipStream_t s) {
+  const bool sc = cd.scaled != 0;
+#define CNSF_CASE(ST, BC, SC)                    \
+  if (storage == ST && g.bc_x == BC && sc == SC) \
+    return launch_update_t<ST, BC, SC, true>(pop, g, ph, cd, parity, lc, phd, partials, fields, s);
   CNSF_CASE(0, 0, false) CNSF_CASE(0, 1, false) CNSF_CASE(0, 2, false)
   CNSF_CASE(1, 0, false) CNSF_CASE(1, 1, false) CNSF_CASE(1, 2, false)
   CNSF_CASE(2, 0, false) CNSF_CASE(2, 1, false) CNSF_CASE(2, 2, false)

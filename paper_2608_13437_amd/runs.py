@@ -54,7 +54,9 @@ def tgv_run(n, *, t_end=None, steps=None, every=10, spectra_at=(), storage=W.STO
     spectra = {}
     status, t0 = "ok", time.perf_counter()
     for s in range(0, steps + 1, every):
-        d = L.diagnostics(spectral=True)
+        E = L.spectrum().tolist() if s in want else None
+        # the first of the next `every` updates also reduces the level it reads
+        d = L.step_diagnostics(every, spectral=True) if s < steps else L.diagnostics(spectral=True)
         hist["step"].append(s)
         hist["t"].append(s * dt)
         for k in HISTORY_KEYS:
@@ -62,10 +64,8 @@ def tgv_run(n, *, t_end=None, steps=None, every=10, spectra_at=(), storage=W.STO
         if d["nonfinite"]:
             status = f"non-finite at t_c = {s * dt:.3f}"
             break
-        if s in want:
-            spectra[f"{s * dt:.4f}"] = L.spectrum().tolist()
-        if s < steps:
-            L.step(every)
+        if E is not None:
+            spectra[f"{s * dt:.4f}"] = E
     wall = time.perf_counter() - t0
     L.close()
     done = hist["step"][-1]

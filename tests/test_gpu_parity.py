@@ -183,6 +183,84 @@ def test_diagnostics_non_power_of_two_axes():
         assert abs(d[k] - o[k]) <= 1e-9 * max(abs(o[k]), 1e-12), (k, d[k], o[k])
 
 
+_STEP_DIAG_CASES = {
+    "random_fp32": (lambda: W.random_case(13, 11, 9, seed=5, sensor=True, amp=0.5), W.STORAGE_FP32, None, 4, 6),
+    "random_fp16": (lambda: W.random_case(13, 11, 9, seed=5, sensor=True, amp=0.5), W.STORAGE_FP16, None, 4, 6),
+    "random_bf16_grid3": (lambda: W.random_case(13, 11, 9, seed=5, sensor=True, amp=0.5), W.STORAGE_BF16,
+                          (256, 1024, 3, True), 4, 6),
+    "random_fp32_block64": (lambda: W.random_case(13, 11, 9, seed=8, sensor=True, amp=0.5), W.STORAGE_FP32,
+                            (64, 64, 0, False), 3, 1),
+    "tgv32_fp16_scaled": (lambda: W.Case("tgv32", dict(W.tgv(32).params, storage_scale=[1.0] * 5 + [2.0 ** -8] * 9),
+                                         W.tgv(32).Q0, 0), W.STORAGE_FP16, None, 20, 10),
+    "sod_walls_fp32": (lambda: W.sod(256, 4, 4), W.STORAGE_FP32, None, 60, 5),
+    "becker_ends_fp16": (lambda: W.becker(128, 4, 4), W.STORAGE_FP16, None, 40, 5),
+}
+
+
+@pytest.mark.parametrize("name", sorted(_STEP_DIAG_CASES))
+def test_step_diagnostics_equals_readout_then_steps(name):
+    """The fused entry point reports the level at entry and leaves the state of n plain steps.
+
+    Populations after the call are bitwise those of step(n); minima, the
+    sensor count and the non-finite count are those of the separate readout
+    exactly; the FP64 sums agree to rounding order (per-block partials of the
+    update grid against the readout's grid-stride partials)."""
+    cnsf = _cnsf()
+    make, storage, launch, warm, n = _STEP_DIAG_CASES[name]
+    case = make()
+    log(f"case {name} storage {storage} launch {launch} warm {warm} n {n}")
+    lat = []
+    for _ in range(2):
+        L = cnsf.Lattice(dict(case.params, storage=storage))
+        if launch is not None:
+            L.set_launch(*launch)
+        L.set_state(case.Q0)
+        L.step(warm)
+        lat.append(L)
+    A, B = lat
+    for spectral in (True, False):
+        dA = A.diagnostics(spectral=spectral)
+        A.step(n)
+        dB = B.step_diagnostics(n, spectral=spectral)
+        log(f"  spectral {spectral}\n    readout {dA}\n    fused   {dB}")
+        assert np.array_equal(A.export_populations()[0], B.export_populations()[0])
+        assert A.info()[:2] == B.info()[:2]
+        for k in ("step", "time", "min_rho", "min_p", "sensor_fraction", "nonfinite"):
+            assert dA[k] == dB[k], k
+        for k in ("mass", "energy", "E_k", "eps_s", "eps_d"):
+            assert abs(dA[k] - dB[k]) <= 1e-12 * max(abs(dA[k]), 1e-300), (k, dA[k], dB[k])
+        for a in range(3):
+            assert abs(dA["momentum"][a] - dB["momentum"][a]) <= 1e-12 * dA["mass"]
+    A.close()
+    B.close()
+
+
+def test_step_diagnostics_sees_the_sensor():
+    """Cells at the Sod shock trip the sensor; the fused count equals the readout's and is not zero."""
+    cnsf = _cnsf()
+    case = W.sod(256, 4, 4)
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    L.step(60)
+    d = L.diagnostics(spectral=False)
+    e = L.step_diagnostics(1, spectral=False)
+    log(f"  sensor fraction readout {d['sensor_fraction']} fused {e['sensor_fraction']}")
+    assert d["sensor_fraction"] > 0
+    assert d["sensor_fraction"] == e["sensor_fraction"]
+    L.close()
+
+
+def test_step_diagnostics_rejects_zero_steps():
+    cnsf = _cnsf()
+    case = W.random_case(8, 8, 8, seed=7)
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    with pytest.raises(cnsf.CnsfError):
+        L.step_diagnostics(0)
+    assert L.info()[0] == 0
+    L.close()
+
+
 def test_conservation_on_gpu():
     cnsf = _cnsf()
     case = W.tgv(32)
