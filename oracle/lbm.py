@@ -30,6 +30,10 @@ Readings where the paper is silent (each listed in the design notes):
   rate: omega_h = omega_b - chi * max(0, omega_b - omega_min).
 * The source enters as w_i dt S_k with no half-step correction.
 * One omega_h relaxes all 98 populations of a cell.
+* No-slip walls (the paper's cases are periodic; it names wall boundaries
+  generated from the declaration as the next step): the wall fixes the
+  momentum, and q_x when adiabatic, by value; every other component returns
+  with the declared normal flux at the wall state.
 
 Pins (tests/test_oracle_pins.py; each checks against something other than
 this code, so no function here is left with parity unpinned):
@@ -49,6 +53,11 @@ this code, so no function here is left with parity unpinned):
   divergence of a prescribed field; with C_sigma = 0 the rate is plain BGK.
 * stream: brute force on 4^3 grids, fixed points, symmetry, the wall equal
   to the mirror-doubled periodic domain, y/z-uniform data equal to 1D.
+* wall_state and the no-slip links: a still adiabatic wall equals the domain
+  doubled with its point-inverted image; gas at rest, and gas moving with
+  the walls, are fixed points; steady Couette flow is linear with
+  tau_xy = mu U/H; steady conduction converges at second order to the
+  linear temperature profile between the wall temperatures.
 
 Array layout: f has shape (14, 7, nz, ny, nx); Q has shape (14, nz, ny, nx).
 """
@@ -71,7 +80,7 @@ TAU = {(0, 0): TXX, (1, 1): TYY, (2, 2): TZZ,
 TAU_PAIRS = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
 
 VISC_CONST, VISC_SUTHERLAND, VISC_POWER = 0, 1, 2
-BC_PERIODIC, BC_WALL, BC_DIRICHLET = 0, 1, 2
+BC_PERIODIC, BC_WALL, BC_DIRICHLET, BC_NOSLIP = 0, 1, 2, 3
 
 # Components odd under the reflection x -> -x: rho u_x, tau_xy, tau_xz, q_x.
 SIGMA_X = np.ones(14)
@@ -224,14 +233,56 @@ def uniform_equilibrium(Qvec, prm):
     return equilibrium(Q, flux(Q, prm), prm)[:, :, 0]
 
 
-def stream(fs, prm):
-    """f_{k,i}(x + c_i) <- f*_{k,i}(x); periodic, or walls / equilibrium ends in x."""
+def wall_state(Qb, prm, side):
+    """The state a no-slip wall imposes next to a boundary cell, and which components it fixes by value.
+
+    The wall moves tangentially with u_w and is either isothermal (T_w > 0) or
+    adiabatic (T_w = 0).  Its state keeps the cell's density, stress and heat
+    flux, takes the wall's velocity and the wall's temperature (the cell's when
+    adiabatic), and has no normal heat flux when adiabatic.  The wall fixes the
+    momentum, and q_x when it is adiabatic; every other component, the energy
+    included, takes its normal flux from the declared flux of Eq. (2) at this
+    state, so an isothermal wall acts through K_q(T_w) T_w, the normal flux of q_x.
+    """
+    uw = np.asarray(prm["wall_u"][side], dtype=np.float64)
+    Tw = float(prm["wall_T"][side])
+    rho, u, E, p, T = primitives(Qb, prm)
+    Tstar = np.full_like(T, Tw) if Tw > 0.0 else T
+    Qw = np.array(Qb, dtype=np.float64, copy=True)
+    for a in range(3):
+        Qw[MX + a] = rho * uw[a]
+    Qw[EN] = rho * Tstar / (prm["gamma"] - 1.0) + 0.5 * rho * float(uw @ uw)
+    by_value = np.zeros(14, dtype=bool)
+    by_value[[MX, MY, MZ]] = True
+    if Tw <= 0.0:
+        Qw[QX] = 0.0
+        by_value[QX] = True
+    return Qw, by_value
+
+
+def stream(fs, prm, Q=None):
+    """f_{k,i}(x + c_i) <- f*_{k,i}(x); periodic, or walls / equilibrium ends in x.
+
+    Q: pre-collision moments of the step (needed by no-slip walls only)."""
     f = np.empty_like(fs)
     for i in range(7):
         # array axes (z, y, x)
         f[:, i] = np.roll(fs[:, i], shift=(C[i, 2], C[i, 1], C[i, 0]), axis=(1, 2, 3))
     bc = prm.get("bc_x", BC_PERIODIC)
-    if bc == BC_WALL:
+    if bc == BC_NOSLIP:
+        # the population leaving through a wall returns along the opposite
+        # link: by value (anti-bounce-back) f_in = -f*_out + 2 w Q_w, by flux
+        # (bounce-back) f_in = f*_out + 2 w c_in Phi_w,x / (c_s^2 lambda)
+        lam = lattice_speed(prm)
+        for side, (x, i_in, i_out, c_in) in enumerate(((0, 1, 2, 1.0), (-1, 2, 1, -1.0))):
+            Qw, by_value = wall_state(Q[..., x], prm, side)
+            Phw = flux(Qw, prm)[:, 0]
+            for k in range(14):
+                if by_value[k]:
+                    f[k, i_in, :, :, x] = -fs[k, i_out, :, :, x] + 2.0 * W[1] * Qw[k]
+                else:
+                    f[k, i_in, :, :, x] = fs[k, i_out, :, :, x] + 2.0 * W[1] * c_in * Phw[k] / (CS2 * lam)
+    elif bc == BC_WALL:
         # halfway bounce-back with the mirror sign of each component
         sig = SIGMA_X.reshape(14, 1, 1)
         f[:, 1, :, :, 0] = sig * fs[:, 2, :, :, 0]
@@ -245,7 +296,8 @@ def stream(fs, prm):
 
 
 def step(f, prm):
-    return stream(collide(f, prm), prm)
+    Q = moments(f) if prm.get("bc_x", BC_PERIODIC) == BC_NOSLIP else None
+    return stream(collide(f, prm), prm, Q)
 
 
 def init_populations(Q, prm):

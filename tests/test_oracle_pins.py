@@ -260,6 +260,86 @@ def test_wall_equals_mirrored_periodic_domain():
     assert _rel(fa, fb[..., :6]) < 1e-13
 
 
+# Point inversion x -> -x (1D data): vectors (rho u, q) change sign, scalars and
+# the stress tensor do not.
+PARITY_P = np.array([1, -1, -1, -1, 1, 1, 1, 1, 1, 1, 1, -1, -1, -1], dtype=np.float64)
+
+
+def test_noslip_still_adiabatic_wall_equals_inverted_doubled_domain():
+    """A still, adiabatic no-slip wall: velocity and normal heat flux vanish at the
+    wall, the mirror image of a point inversion.  On y,z-uniform data the wall
+    run equals the periodic run of the domain doubled with its inverted image."""
+    c = W.smooth_random_case(7, 1, 1, seed=31, sensor=True, amp=0.3)
+    prm = dict(c.params)
+    prm.update(bc_x=W.BC_NOSLIP, wall_u=[[0.0] * 3, [0.0] * 3], wall_T=[0.0, 0.0])
+    Qd = np.concatenate([c.Q0, PARITY_P.reshape(14, 1, 1, 1) * c.Q0[..., ::-1]], axis=3)
+    prd = dict(prm, bc_x=W.BC_PERIODIC, nx=14)
+    n = 25
+    fa = lbm.moments(lbm.run(c.Q0, prm, n))
+    fb = lbm.moments(lbm.run(Qd, prd, n))
+    assert _rel(fa, fb[..., :7]) < 1e-13
+
+
+@pytest.mark.parametrize("wall_T", [(1.3, 1.3), (0.0, 0.0), (1.3, 0.0)])
+def test_gas_at_rest_between_still_noslip_walls_is_fixed_point(wall_T):
+    prm = W.random_params(6, 2, 2, sensor=True)
+    prm.update(bc_x=W.BC_NOSLIP, wall_u=[[0.0] * 3, [0.0] * 3], wall_T=list(wall_T))
+    Qv = W.uniform_state(0.9, (0.0, 0.0, 0.0), 0.9 * 1.3, prm["gamma"])   # T = 1.3
+    Q = np.broadcast_to(np.array(Qv).reshape(14, 1, 1, 1), (14, 2, 2, 6)).copy()
+    f = lbm.run(Q, prm, 10)
+    assert _rel(lbm.moments(f), Q) < 1e-14
+
+
+@pytest.mark.parametrize("wall_T", [(0.8, 0.8), (0.0, 0.8)])
+def test_flow_moving_with_noslip_walls_is_fixed_point(wall_T):
+    """Gas moving with both walls (the walls' velocity, the isothermal wall's
+    temperature): the returning links carry the flow's own fluxes."""
+    prm = W.random_params(6, 2, 2, sensor=True)
+    uw = [0.0, 0.25, -0.15]
+    prm.update(bc_x=W.BC_NOSLIP, wall_u=[uw, uw], wall_T=list(wall_T))
+    Qv = W.uniform_state(1.25, tuple(uw), 1.25 * 0.8, prm["gamma"])          # T = 0.8
+    Q = np.broadcast_to(np.array(Qv).reshape(14, 1, 1, 1), (14, 2, 2, 6)).copy()
+    f = lbm.run(Q, prm, 10)
+    assert _rel(lbm.moments(f), Q) < 1e-14
+
+
+def test_low_mach_couette_flow_is_linear():
+    """Steady Couette flow between a still and a moving isothermal wall: u_y = U x/H
+    and tau_xy = mu U/H (closed form of the steady relaxed system with constant
+    viscosity); at U = 0.02 the viscous heating changes rho by ~1e-5.  Mass is
+    conserved to round-off."""
+    n, U = 8, 0.02
+    prm = W.couette_params(n, U=U, f_mu=0.01)
+    x = (np.arange(n) + 0.5) / n
+    sh = (1, 1, n)
+    one, zero = np.ones(sh), np.zeros(sh)
+    Q = W.conserved(one, zero, (U * x).reshape(sh), zero, one, prm["gamma"])
+    f = lbm.run(Q, prm, int(round(4.0 / prm["dt"])))
+    Qn = lbm.moments(f)
+    rho, u, E, p, T = lbm.primitives(Qn, prm)
+    assert np.abs(u[1, 0, 0] - U * x).max() < 1e-6 * U
+    assert np.abs(Qn[lbm.TXY] / (prm["mu0"] * U) - 1.0).max() < 1e-5
+    assert abs(Qn[0].sum() / Q[0].sum() - 1.0) < 1e-14
+
+
+def test_steady_conduction_between_isothermal_walls_converges_second_order():
+    """Gas at rest between walls at T = 1 and 1.2: the steady state has uniform p,
+    q_x = -kappa dT/dx and T linear between the wall temperatures.  The error
+    of the lattice solution falls by more than 3x per halving of dx."""
+    err = []
+    for n in (8, 16):
+        prm = W.couette_params(n, U=0.0, T_L=1.0, T_R=1.2, f_mu=0.01)
+        x = (np.arange(n) + 0.5) / n
+        T_exact = 1.0 + 0.2 * x
+        sh = (1, 1, n)
+        zero = np.zeros(sh)
+        Q = W.conserved((1.0 / T_exact).reshape(sh), zero, zero, zero, np.ones(sh), prm["gamma"])
+        Qn = lbm.moments(lbm.run(Q, prm, int(round(6.0 / prm["dt"]))))
+        T = lbm.primitives(Qn, prm)[4][0, 0]
+        err.append(np.abs(T - T_exact).max())
+    assert err[1] < 1e-3 and err[0] / err[1] > 3.0, err
+
+
 def test_yz_uniform_data_equals_1d_run():
     c = W.sod(64, 3, 2, steps=0)
     c1 = W.sod(64, 1, 1, steps=0)

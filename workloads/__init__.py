@@ -31,7 +31,7 @@ COMPONENT_NAMES = (
 )
 
 VISC_CONST, VISC_SUTHERLAND, VISC_POWER = 0, 1, 2
-BC_PERIODIC, BC_WALL, BC_DIRICHLET = 0, 1, 2
+BC_PERIODIC, BC_WALL, BC_DIRICHLET, BC_NOSLIP = 0, 1, 2, 3
 STORAGE_FP32, STORAGE_FP16, STORAGE_BF16 = 0, 1, 2
 
 # Largest characteristic speed |u*| + c*_R of the exact Sod Riemann solution
@@ -57,6 +57,7 @@ def default_params(nx: int, ny: int, nz: int) -> dict:
         Q_ref=[0.0] * NCOMP,
         storage_scale=[0.0] * NCOMP,
         a_ref=0.0,
+        wall_u=[[0.0] * 3, [0.0] * 3], wall_T=[0.0, 0.0],
     )
 
 
@@ -221,6 +222,43 @@ def smooth_random_case(nx, ny, nz, seed=0, *, steps=100, modes=3, amp=0.2, senso
     u, v, w = (amp * field() for _ in range(3))
     Q = conserved(rho, u, v, w, p, prm["gamma"])
     return Case(f"smooth{nx}x{ny}x{nz}_s{seed}", prm, Q, steps)
+
+
+def noslip_case(nx, ny, nz, seed=0, *, steps=100, amp=0.2, sensor=True,
+                wall_u=((0.0, 0.1, -0.05), (0.0, 0.2, 0.1)), wall_T=(0.0, 1.1)):
+    """Smooth random field between no-slip walls at x = 0 and x = nx dx.
+
+    By default the wall at x = 0 is adiabatic and the one at x = nx dx
+    isothermal, and both move tangentially, so every term of the wall rule
+    is active."""
+    c = smooth_random_case(nx, ny, nz, seed, steps=steps, amp=amp, sensor=sensor)
+    prm = dict(c.params)
+    prm.update(bc_x=BC_NOSLIP, wall_u=[list(map(float, w)) for w in wall_u], wall_T=[float(t) for t in wall_T])
+    return Case(f"noslip{nx}x{ny}x{nz}_s{seed}", prm, c.Q0, steps)
+
+
+def couette_params(n, ny=1, nz=1, *, U=0.02, T_L=1.0, T_R=1.0, mu=0.05, Pr=0.71, gamma=1.4,
+                   f_mu=0.05, CFL=0.1):
+    """Gas between no-slip isothermal walls at x = 0 (at rest, T_L) and x = 1 (moving
+    with U along y, T_R); constant viscosity, dx = 1/n, tau_R = tau_q = 5 dt."""
+    prm = default_params(n, ny, nz)
+    dx = 1.0 / n
+    prm.update(dx=dx, gamma=gamma, mu0=mu, T_ref=1.0, visc_law=VISC_CONST, prandtl=Pr, f_mu=f_mu,
+               bc_x=BC_NOSLIP, wall_u=[[0.0, 0.0, 0.0], [0.0, float(U), 0.0]], wall_T=[float(T_L), float(T_R)])
+    Tmax = max(T_L, T_R)
+    dt = CFL * dx / (np.sqrt(gamma * Tmax) + abs(U))
+    for _ in range(200):
+        prm["tau_R"] = prm["tau_q"] = 5.0 * dt
+        a = float(char_speed(1.0 / Tmax, abs(U), 1.0, prm))
+        dt_new = CFL * dx / a
+        if abs(dt_new - dt) < 1e-14 * dt:
+            dt = dt_new
+            break
+        dt = 0.5 * (dt + dt_new)
+    prm["dt"] = dt
+    prm["tau_R"] = prm["tau_q"] = 5.0 * dt
+    prm["a_ref"] = CFL * dx / dt
+    return prm
 
 
 # --------------------------------------------------------------------------
