@@ -140,6 +140,41 @@ def diagnostics_timing(L, reps=3):
     return round(a.elapsed_time(b) / reps, 3)
 
 
+def noslip_timing(cnsf, L, n, storage, Qdev, steps, warmup):
+    """The same update with no-slip x-walls (adiabatic and still at x = 0,
+    isothermal and moving at x = L) on the same state and in the same
+    population array as the periodic timing, so both see one placement."""
+    import workloads as W
+    prm = W.tgv_params(n, storage=STORAGES[storage])
+    prm.update(bc_x=W.BC_NOSLIP, wall_u=[[0.0, 0.0, 0.0], [0.0, 0.5, 0.0]], wall_T=[0.0, prm["T_ref"]])
+    Lw = cnsf.Lattice(prm, buf=L.buf)
+    Lw.set_state(Qdev)
+    ms = time_update(Lw, steps, warmup)[0]
+    finite = Lw.diagnostics(spectral=False)["nonfinite"] == 0
+    Lw.close()
+    del Lw
+    return ms, finite
+
+
+def fused_readout_timing(L, reps=4):
+    """Added cost of the same readout when the first update of a step reduces it
+    (cnsf_step_diagnostics): one fused call of one step less one plain step,
+    HIP events on the lattice's stream; even reps cover both streaming passes."""
+    import torch
+    L.step_diagnostics(1, spectral=True)
+    torch.cuda.synchronize()
+    ms = []
+    for fn in (lambda: L.step_diagnostics(1, spectral=True), lambda: L.step(1)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b) / reps)
+    return round(ms[0] - ms[1], 3)
+
+
 def copy_bandwidth(cnsf, nbytes=8 << 30, reps=10):
     import torch
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -225,6 +260,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-placement", action="store_true", help="skip the second-allocation timing")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the shell-spectrum timing")
+    ap.add_argument("--no-walls", action="store_true", help="skip the no-slip wall timing")
     ap.add_argument("--copy-only", type=int, default=0, metavar="GIB",
                     help="only run the plain copy kernel on GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -252,6 +288,7 @@ def main():
     Qdev = tgv_field_device(n)
     cells = n ** 3
     res = {}
+    walls = {}
     for st in storages:
         L, prm = load_lattice_tgv(cnsf, n, st, Qdev)
         launch = L.get_launch()
@@ -263,11 +300,18 @@ def main():
         if st == head and not args.no_spectrum:
             spectrum = spectrum_timing(L, st)
             spectrum["diagnostics_ms"] = diagnostics_timing(L)
+            spectrum["fused_diagnostics_ms"] = fused_readout_timing(L)
         d = L.diagnostics(spectral=False)
         alg_bytes = 98 * 2 * BYTES_PER_POP[st] * cells
         res[st] = dict(ms=mean_ms, min_ms=min_ms, wall=wall, mlups=cells / (mean_ms * 1e-3) / 1e6, launch=launch,
                        gbps=alg_bytes / (mean_ms * 1e-3) / 1e9, bytes=alg_bytes, finite=d["nonfinite"] == 0)
         log(f"  {st}: {mean_ms:.3f} ms/step, {res[st]['mlups']:.0f} MLUPS, {res[st]['gbps']:.0f} GB/s")
+        if not args.no_walls and st in ("fp32", "fp16"):
+            wms, wfin = noslip_timing(cnsf, L, n, st, Qdev, max(2, args.steps // 4), args.warmup)
+            walls[st] = dict(ms_per_step=round(wms, 4), MLUPS=round(cells / (wms * 1e-3) / 1e6, 1),
+                             GBps=round(alg_bytes / (wms * 1e-3) / 1e9, 1), vs_periodic=round(mean_ms / wms, 4),
+                             finite=wfin)
+            log(f"  {st} no-slip walls: {wms:.3f} ms/step ({mean_ms / wms:.3f}x the periodic rate)")
         L.close()
         del L
         torch.cuda.empty_cache()
@@ -318,6 +362,9 @@ def main():
     if placement is not None:
         out["placement"] = {"storage": head, "ms_per_step": [round(x, 4) for x in placement],
                             "note": "same state in two coexisting allocations; value is the first"}
+    if walls:
+        out["noslip_walls"] = dict(walls, note="no-slip x-walls (still adiabatic, moving isothermal): same state "
+                                               "and population array as the periodic figure")
     if not args.no_batch:
         out["batch"] = run_batch(cnsf, 20, 4)
     if not args.no_cpu:

@@ -48,7 +48,7 @@ enum cnsf_status {
 };
 
 enum cnsf_visc_law { CNSF_VISC_CONST = 0, CNSF_VISC_SUTHERLAND = 1, CNSF_VISC_POWER = 2 };
-enum cnsf_bc { CNSF_BC_PERIODIC = 0, CNSF_BC_WALL = 1, CNSF_BC_DIRICHLET = 2 };
+enum cnsf_bc { CNSF_BC_PERIODIC = 0, CNSF_BC_WALL = 1, CNSF_BC_DIRICHLET = 2, CNSF_BC_NOSLIP = 3 };
 enum cnsf_storage { CNSF_STORAGE_FP32 = 0, CNSF_STORAGE_FP16 = 1, CNSF_STORAGE_BF16 = 2 };
 enum cnsf_where { CNSF_HOST = 0, CNSF_DEVICE = 1 };
 
@@ -73,8 +73,14 @@ enum cnsf_where { CNSF_HOST = 0, CNSF_DEVICE = 1 };
  *  C_sigma, J_min, omega_min  sensor slope, threshold and rate floor of
  *                  Eqs. (3)-(5); C_sigma = 0 disables the sensor.
  *  bc_x            x-ends: PERIODIC; WALL (halfway bounce-back with the mirror
- *                  sign of each component); DIRICHLET (incoming populations set
- *                  to the equilibrium of Q_left / Q_right).  y and z periodic.
+ *                  sign of each component: a slip, adiabatic symmetry plane);
+ *                  DIRICHLET (incoming populations set to the equilibrium of
+ *                  Q_left / Q_right); NOSLIP (halfway no-slip walls generated
+ *                  from the fluxes of Eq. (2): the momentum takes the wall's
+ *                  velocity and, on an adiabatic wall, q_x is zero, both by
+ *                  anti-bounce-back; every other component returns with its
+ *                  Eq. (2) normal flux at the wall state, by bounce-back).
+ *                  y and z periodic.
  *  Q_left, Q_right uniform 14-vectors for DIRICHLET.
  *  storage         population storage: FP32, or FP16 / BF16 deviations.
  *  Q_ref           reference state of the shifted storage: populations are
@@ -82,6 +88,9 @@ enum cnsf_where { CNSF_HOST = 0, CNSF_DEVICE = 1 };
  *  storage_scale   s_k per component (power of two recommended); 0 means 1.
  *  a_ref           optional largest characteristic speed; if > 0, creation
  *                  rejects a_ref dt/dx > 1/2 (sub-characteristic bound).
+ *  wall_u[s]       NOSLIP: velocity of the wall at x = 0 (s = 0) and at
+ *                  x = nx*dx (s = 1); tangential, so wall_u[s][0] must be 0.
+ *  wall_T[s]       NOSLIP: wall temperature (> 0, isothermal) or 0 (adiabatic).
  */
 typedef struct cnsf_params {
   uint32_t size;
@@ -101,6 +110,8 @@ typedef struct cnsf_params {
   double Q_ref[CNSF_NCOMP];
   double storage_scale[CNSF_NCOMP];
   double a_ref;
+  double wall_u[2][3];
+  double wall_T[2];
 } cnsf_params;
 
 /* Volume diagnostics (FP64 reductions on the device).  E_k, eps_s, eps_d follow

@@ -45,6 +45,8 @@ class cnsf_params(C.Structure):
         ("Q_ref", D14),
         ("storage_scale", D14),
         ("a_ref", C.c_double),
+        ("wall_u", (C.c_double * 3) * 2),
+        ("wall_T", C.c_double * 2),
     ]
 
 
@@ -239,6 +241,13 @@ def make_params(prm: dict) -> cnsf_params:
             arr = getattr(p, name)
             for k in range(NCOMP):
                 arr[k] = float(v[k])
+        elif name == "wall_u":
+            for s in range(2):
+                for a in range(3):
+                    p.wall_u[s][a] = float(v[s][a])
+        elif name == "wall_T":
+            for s in range(2):
+                p.wall_T[s] = float(v[s])
         elif name in ("nx", "ny", "nz", "visc_law", "bc_x", "storage"):
             setattr(p, name, int(v))
         else:
@@ -260,13 +269,20 @@ def _stream_handle(stream=None) -> int:
 class Lattice:
     """One lattice on the current HIP device; populations in a torch-owned buffer."""
 
-    def __init__(self, prm: dict, *, device="cuda", stream=None):
+    def __init__(self, prm: dict, *, device="cuda", stream=None, buf=None):
+        """buf: optional uint8 CUDA tensor of at least the required bytes to hold the
+        populations (e.g. another lattice's, whose state this one then overwrites)."""
         torch = _torch()
         self.prm = dict(prm)
         self.p = make_params(prm)
         self.nbytes = cnsf_required_bytes(self.p)
-        self.device = torch.device(device)
-        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.device = torch.device(device) if buf is None else buf.device
+        if buf is not None:
+            if buf.dtype != torch.uint8 or not buf.is_cuda or buf.numel() < self.nbytes or not buf.is_contiguous():
+                raise ValueError(f"buf must be a contiguous uint8 CUDA tensor of >= {self.nbytes} bytes")
+            self.buf = buf
+        else:
+            self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream
         self.h = cnsf_create(self.p, self.buf.data_ptr(), self.nbytes, _stream_handle(stream))
         self.shape = (self.p.nz, self.p.ny, self.p.nx)

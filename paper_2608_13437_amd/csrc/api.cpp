@@ -89,7 +89,7 @@ int validate(const cnsf_params* p) {
   if (!(p->omega_min > 0.0 && p->omega_min <= 2.0))
     return fail(CNSF_E_INVALID, "omega_min = %g outside (0, 2]", p->omega_min);
   if (p->C_sigma > 0.0 && p->mu0 <= 0.0) return fail(CNSF_E_INVALID, "the sensor needs mu0 > 0");
-  if (p->bc_x < 0 || p->bc_x > 2) return fail(CNSF_E_INVALID, "bc_x %d unknown", p->bc_x);
+  if (p->bc_x < 0 || p->bc_x > 3) return fail(CNSF_E_INVALID, "bc_x %d unknown", p->bc_x);
   if (p->storage < 0 || p->storage > 2) return fail(CNSF_E_INVALID, "storage %d unknown", p->storage);
   for (int k = 0; k < NC; ++k)
     if (!(std::isfinite(p->storage_scale[k]) && p->storage_scale[k] >= 0.0))
@@ -106,6 +106,16 @@ int validate(const cnsf_params* p) {
   if (p->a_ref > 0.0 && p->a_ref * p->dt / p->dx > 0.5 * (1.0 + 1e-12))
     return fail(CNSF_E_INVALID, "a_ref dt / dx = %g exceeds the sub-characteristic bound 1/2",
                 p->a_ref * p->dt / p->dx);
+  if (p->bc_x == CNSF_BC_NOSLIP) {
+    for (int s = 0; s < 2; ++s) {
+      for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->wall_u[s][a])) return fail(CNSF_E_INVALID, "wall_u[%d][%d] is not finite", s, a);
+      if (p->wall_u[s][0] != 0.0)
+        return fail(CNSF_E_INVALID, "wall_u[%d][0] = %g: a wall moves tangentially only", s, p->wall_u[s][0]);
+      if (!(std::isfinite(p->wall_T[s]) && p->wall_T[s] >= 0.0))
+        return fail(CNSF_E_INVALID, "wall_T[%d] = %g must be > 0 (isothermal) or 0 (adiabatic)", s, p->wall_T[s]);
+    }
+  }
   if (p->bc_x == CNSF_BC_DIRICHLET) {
     for (const double* Qe : {p->Q_left, p->Q_right}) {
       const double rho = Qe[0];
@@ -205,6 +215,20 @@ Geom derive_geom(const cnsf_params* p, const PhysD& ph) {
     for (int k = 0; k < NC; ++k) {
       g.dev_left[k] = (float)(fl[k][1] - feq_ref<double>(cd, k, 1));
       g.dev_right[k] = (float)(fr[k][2] - feq_ref<double>(cd, k, 2));
+    }
+  }
+  if (p->bc_x == CNSF_BC_NOSLIP) {
+    const Codec cd = derive_codec(p, ph);
+    for (int s = 0; s < 2; ++s) {
+      const double Tw = p->wall_T[s];
+      g.wall_uy[s] = (float)p->wall_u[s][1];
+      g.wall_uz[s] = (float)p->wall_u[s][2];
+      g.wall_iso[s] = Tw > 0.0 ? 1 : 0;
+      if (Tw > 0.0) {
+        const double mu = mu_of_T<double>(Tw, ph);
+        g.wall_nuR[s] = (float)(mu * ph.inv_tauR);
+        g.wall_dKT[s] = (float)(ph.kq_over_mu0 * mu * Tw - (double)cd.KT_ref);
+      }
     }
   }
   return g;

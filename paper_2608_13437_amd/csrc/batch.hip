@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) k_batch_update(typename Store<ST>::T* __r
       float gv[NC][NV];
       gather<ST, 0, SC, float>(pop, g, M.cd, n, parity, off, gv);
       update_cell(gv, M.cd, M.ph);
-      scatter<ST, 0, SC>(pop, g, M.cd, n, parity, off, gv);
+      scatter<ST, 0, SC>(pop, g, M.cd, M.ph, WallCell{}, n, parity, off, gv);
     }
   }
 }

@@ -41,9 +41,13 @@ struct Geom {
   uint32_t nx, ny, nz, nxy, ncells;
   uint32_t pad_;
   uint64_t cstride;        // elements between the regions of consecutive components
-  int32_t bc_x;            // 0 periodic, 1 wall, 2 equilibrium ends
+  int32_t bc_x;            // 0 periodic, 1 parity wall, 2 equilibrium ends, 3 no-slip wall
   float dev_left[NC];      // f^eq_{k,+x}(Q_left) - f^eq_{k,+x}(Q_ref): enters at x = 0
   float dev_right[NC];     // f^eq_{k,-x}(Q_right) - f^eq_{k,-x}(Q_ref): enters at x = nx-1
+  // no-slip walls, [0] at x = 0 and [1] at x = nx-1: tangential velocity,
+  // isothermal flag, and for isothermal walls nu_R(T_w) and K_q(T_w) T_w - (K_q T)_ref
+  float wall_uy[2], wall_uz[2], wall_nuR[2], wall_dKT[2];
+  int32_t wall_iso[2];
 };
 
 // Physical constants of the update, in the precision of the arithmetic.
@@ -318,11 +322,25 @@ __device__ inline void collide_dev(float g[NV], const float dQ[NC], const float 
   }
 }
 
-// The whole cell update on shifted populations (FP32).
-__device__ inline void update_cell(float g[NC][NV], const Codec& cd, const Phys& ph, float* chi_out = nullptr) {
+// Pre-collision values of a cell that a no-slip wall next to it needs.
+struct WallCell {
+  float rho, nuR, txy, txz, qx;
+};
+
+// The whole cell update on shifted populations (FP32).  `wc`, if given,
+// receives the values a no-slip wall takes from the cell.
+__device__ inline void update_cell(float g[NC][NV], const Codec& cd, const Phys& ph, float* chi_out = nullptr,
+                                   WallCell* wc = nullptr) {
   float dQ[NC], Q[NC];
   DevPrim P;
   const float omega = cell_state(g, cd, ph, dQ, Q, P, chi_out);
+  if (wc) {
+    wc->rho = P.rho;
+    wc->nuR = P.nuR;
+    wc->txy = Q[8];
+    wc->txz = Q[9];
+    wc->qx = Q[11];
+  }
   collide_dev<0>(g[0], dQ, Q, P, ph, omega);
   collide_dev<1>(g[1], dQ, Q, P, ph, omega);
   collide_dev<2>(g[2], dQ, Q, P, ph, omega);
@@ -447,11 +465,12 @@ __device__ inline void stream_offsets(const Geom& g, const Nbr& n, int parity, u
 }
 
 // Gather the 98 shifted populations g = f - f^eq(Q_ref) of the current time
-// level.  BC: 0 periodic, 1 wall, 2 equilibrium ends.  A link that crossed a
-// wall returns reversed with the mirror sign of its component; the reference
-// shift is mirror-symmetric in x, so the shifted value simply changes sign
-// for the x-odd components.  At an equilibrium end the link is the end
-// state's equilibrium.
+// level.  BC: 0 periodic, 1 parity wall, 2 equilibrium ends, 3 no-slip wall.
+// A link that crossed a parity wall returns reversed with the mirror sign of
+// its component; the reference shift is mirror-symmetric in x, so the shifted
+// value simply changes sign for the x-odd components.  At an equilibrium end
+// the link is the end state's equilibrium.  At a no-slip wall the emitting
+// cell already stored the returned link.
 template <int ST, int BC, bool SC, typename R>
 __device__ inline void gather(const typename Store<ST>::T* __restrict__ pop, const Geom& g, const Codec& cd,
                               const Nbr& n, int parity, const uint32_t off[NV], R gv[NC][NV]) {
@@ -471,21 +490,64 @@ __device__ inline void gather(const typename Store<ST>::T* __restrict__ pop, con
   }
 }
 
+// No-slip wall: side (0 at x = 0, 1 at x = nx-1) through which the cell emits
+// link i, or -1.  The emitting cell turns the link round in both passes; the
+// next pass reads it back unchanged.
+template <int BC>
+__device__ inline int noslip_side(const Geom& g, const Nbr& n, int i) {
+  if (BC != 3) return -1;
+  if (i == 2 && n.x == 0) return 0;
+  if (i == 1 && n.x == g.nx - 1) return 1;
+  return -1;
+}
+
+// The link of component k returning from no-slip wall s, in shifted form, from
+// the outgoing g*.  The wall fixes the momentum (rho u_w) and, when adiabatic,
+// q_x = 0: anti-bounce-back, f_in = -f*_out + 2 w_1 Q_w.  Every other component
+// returns with the normal flux of Eq. (2) at the wall state (the cell's rho,
+// tau, q; the wall's velocity; T_w when isothermal): f_in = f*_out +
+// 2 w_1 c_in Phi_w / (c_s^2 lambda).  The reference shift cancels except in
+// q_x's flux, hence K_q T_w - (K_q T)_ref.
+__device__ inline float noslip_link(int k, float v, int s, const Geom& g, const Phys& ph, const WallCell& w) {
+  const float F = (s == 0 ? 0.25f : -0.25f) * ph.four_over_lam;   // 2 w_1 c_in / (c_s^2 lambda)
+  const bool iso = g.wall_iso[s] != 0;
+  const float uy = g.wall_uy[s], uz = g.wall_uz[s];
+  const float nuR = iso ? g.wall_nuR[s] : w.nuR;
+  switch (k) {
+    case 1: return -v;
+    case 2: return -v + 0.25f * w.rho * uy;
+    case 3: return -v + 0.25f * w.rho * uz;
+    case 4: return v + F * ((iso ? w.qx : 0.0f) - (w.txy * uy + w.txz * uz));
+    case 8: return v - F * nuR * uy;
+    case 9: return v - F * nuR * uz;
+    case 11: return iso ? v + F * g.wall_dKT[s] : -v;
+    default: return v;
+  }
+}
+
 // Write g*_i to off[opp(i)] (see stream_offsets).  A link leaving through an
 // x-end is stored back into the cell as the opposite direction: mirrored at a
-// wall, replaced by the end state's equilibrium at an equilibrium end.
+// parity wall, replaced by the end state's equilibrium at an equilibrium end,
+// turned round by the no-slip rule (`ph`, `w` used only there).
 template <int ST, int BC, bool SC>
-__device__ inline void scatter(typename Store<ST>::T* __restrict__ pop, const Geom& g, const Codec& cd, const Nbr& n,
-                               int parity, const uint32_t off[NV], const float gv[NC][NV]) {
+__device__ inline void scatter(typename Store<ST>::T* __restrict__ pop, const Geom& g, const Codec& cd,
+                               const Phys& ph, const WallCell& w, const Nbr& n, int parity, const uint32_t off[NV],
+                               const float gv[NC][NV]) {
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     const __amdgpu_buffer_rsrc_t rs = component_rsrc<ST>(pop, g, k);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       float v = gv[k][i];
-      if (crossed_end<BC>(g, n, parity, opp(i))) {
-        if (BC == 1 && x_odd(k)) v = -v;
-        if (BC == 2) v = (i == 2) ? g.dev_left[k] : g.dev_right[k];
+      if (BC == 1 || BC == 2) {
+        if (crossed_end<BC>(g, n, parity, opp(i))) {
+          if (BC == 1 && x_odd(k)) v = -v;
+          if (BC == 2) v = (i == 2) ? g.dev_left[k] : g.dev_right[k];
+        }
+      }
+      if (BC == 3) {
+        const int s = noslip_side<BC>(g, n, i);
+        if (s >= 0) v = noslip_link(k, v, s, g, ph, w);
       }
       if (ST != 0 && SC) v *= cd.inv_scale[k];
       buf_store<ST>(rs, off[opp(i)], v);

@@ -464,9 +464,9 @@ hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const P
                             const Codec& cd, int parity, DiagPartial* partials, double* fields, hipStream_t s) {
 #define CNSF_CASE(ST, BC) \
   if (storage == ST && g.bc_x == BC) return diag_sums_t<ST, BC>(pop, g, ph, phd, cd, parity, partials, fields, s);
-  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2)
-  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2)
-  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2)
+  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2) CNSF_CASE(0, 3)
+  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2) CNSF_CASE(1, 3)
+  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2) CNSF_CASE(2, 3)
 #undef CNSF_CASE
   return hipErrorInvalidValue;
 }

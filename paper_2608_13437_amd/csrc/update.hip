@@ -61,15 +61,16 @@ __global__ void __launch_bounds__(256) k_update(typename Store<ST>::T* __restric
       stream_offsets<ST, BC>(g, n, parity, off);
       float gv[NC][NV];
       gather<ST, BC, SC, float>(pop, g, cd, n, parity, off, gv);
+      WallCell wc{};
       if constexpr (DIAG) {
         cell_sums(gv, cd, phd, c, g.ncells, fields, acc);
         float chi = 0.0f;
-        update_cell(gv, cd, ph, &chi);
+        update_cell(gv, cd, ph, &chi, BC == 3 ? &wc : nullptr);
         acc.sensor += chi > 0.0f ? 1.0 : 0.0;
       } else {
-        update_cell(gv, cd, ph);
+        update_cell(gv, cd, ph, nullptr, BC == 3 ? &wc : nullptr);
       }
-      scatter<ST, BC, SC>(pop, g, cd, n, parity, off, gv);
+      scatter<ST, BC, SC>(pop, g, cd, ph, wc, n, parity, off, gv);
     }
   }
   if constexpr (DIAG) {
@@ -202,11 +203,11 @@ hipError_t launch_update(int storage, void* pop, const Geom& g, const Phys& ph, 
 #define CNSF_CASE(ST, BC, SC)                              \
   if (storage == ST && g.bc_x == BC && sc == SC)           \
     return launch_update_t<ST, BC, SC, false>(pop, g, ph, cd, parity, lc, none, nullptr, nullptr, s);
-  CNSF_CASE(0, 0, false) CNSF_CASE(0, 1, false) CNSF_CASE(0, 2, false)
-  CNSF_CASE(1, 0, false) CNSF_CASE(1, 1, false) CNSF_CASE(1, 2, false)
-  CNSF_CASE(2, 0, false) CNSF_CASE(2, 1, false) CNSF_CASE(2, 2, false)
-  CNSF_CASE(1, 0, true) CNSF_CASE(1, 1, true) CNSF_CASE(1, 2, true)
-  CNSF_CASE(2, 0, true) CNSF_CASE(2, 1, true) CNSF_CASE(2, 2, true)
+  CNSF_CASE(0, 0, false) CNSF_CASE(0, 1, false) CNSF_CASE(0, 2, false) CNSF_CASE(0, 3, false)
+  CNSF_CASE(1, 0, false) CNSF_CASE(1, 1, false) CNSF_CASE(1, 2, false) CNSF_CASE(1, 3, false)
+  CNSF_CASE(2, 0, false) CNSF_CASE(2, 1, false) CNSF_CASE(2, 2, false) CNSF_CASE(2, 3, false)
+  CNSF_CASE(1, 0, true) CNSF_CASE(1, 1, true) CNSF_CASE(1, 2, true) CNSF_CASE(1, 3, true)
+  CNSF_CASE(2, 0, true) CNSF_CASE(2, 1, true) CNSF_CASE(2, 2, true) CNSF_CASE(2, 3, true)
 #undef CNSF_CASE
   return hipErrorInvalidValue;
 }
@@ -218,11 +219,11 @@ hipError_t launch_update_diag(int storage, void* pop, const Geom& g, const Phys&
 #define CNSF_CASE(ST, BC, SC)                    \
   if (storage == ST && g.bc_x == BC && sc == SC) \
     return launch_update_t<ST, BC, SC, true>(pop, g, ph, cd, parity, lc, phd, partials, fields, s);
-  CNSF_CASE(0, 0, false) CNSF_CASE(0, 1, false) CNSF_CASE(0, 2, false)
-  CNSF_CASE(1, 0, false) CNSF_CASE(1, 1, false) CNSF_CASE(1, 2, false)
-  CNSF_CASE(2, 0, false) CNSF_CASE(2, 1, false) CNSF_CASE(2, 2, false)
-  CNSF_CASE(1, 0, true) CNSF_CASE(1, 1, true) CNSF_CASE(1, 2, true)
-  CNSF_CASE(2, 0, true) CNSF_CASE(2, 1, true) CNSF_CASE(2, 2, true)
+  CNSF_CASE(0, 0, false) CNSF_CASE(0, 1, false) CNSF_CASE(0, 2, false) CNSF_CASE(0, 3, false)
+  CNSF_CASE(1, 0, false) CNSF_CASE(1, 1, false) CNSF_CASE(1, 2, false) CNSF_CASE(1, 3, false)
+  CNSF_CASE(2, 0, false) CNSF_CASE(2, 1, false) CNSF_CASE(2, 2, false) CNSF_CASE(2, 3, false)
+  CNSF_CASE(1, 0, true) CNSF_CASE(1, 1, true) CNSF_CASE(1, 2, true) CNSF_CASE(1, 3, true)
+  CNSF_CASE(2, 0, true) CNSF_CASE(2, 1, true) CNSF_CASE(2, 2, true) CNSF_CASE(2, 3, true)
 #undef CNSF_CASE
   return hipErrorInvalidValue;
 }
@@ -258,9 +259,9 @@ hipError_t launch_primitives(int storage, const void* pop, double* out, const Ge
                              int parity, uint32_t cell0, uint32_t nslab, hipStream_t s) {
 #define CNSF_CASE(ST, BC) \
   if (storage == ST && g.bc_x == BC) return launch_primitives_t<ST, BC>(pop, out, g, cd, ph, parity, cell0, nslab, s);
-  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2)
-  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2)
-  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2)
+  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2) CNSF_CASE(0, 3)
+  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2) CNSF_CASE(1, 3)
+  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2) CNSF_CASE(2, 3)
 #undef CNSF_CASE
   return hipErrorInvalidValue;
 }
@@ -280,9 +281,9 @@ hipError_t launch_moments(int storage, const void* pop, double* out, const Geom&
                           uint32_t cell0, uint32_t nslab, hipStream_t s) {
 #define CNSF_CASE(ST, BC) \
   if (storage == ST && g.bc_x == BC) return launch_moments_t<ST, BC>(pop, out, g, cd, parity, cell0, nslab, s);
-  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2)
-  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2)
-  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2)
+  CNSF_CASE(0, 0) CNSF_CASE(0, 1) CNSF_CASE(0, 2) CNSF_CASE(0, 3)
+  CNSF_CASE(1, 0) CNSF_CASE(1, 1) CNSF_CASE(1, 2) CNSF_CASE(1, 3)
+  CNSF_CASE(2, 0) CNSF_CASE(2, 1) CNSF_CASE(2, 2) CNSF_CASE(2, 3)
 #undef CNSF_CASE
   return hipErrorInvalidValue;
 }

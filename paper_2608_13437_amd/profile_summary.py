@@ -11,6 +11,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -44,13 +45,18 @@ def stats(path, out, command, bench_log=None):
     open(out, "w").write("\n".join(lines) + "\n")
 
 
-def counter(path, name_sub):
-    return [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if name_sub in r["Kernel_Name"]]
+# the periodic update without the fused diagnostics: k_update<storage, 0, scaled, parity, false>
+UPDATE = re.compile(r"k_update<\d, 0, (false|true), [01], false>")
+COPY = re.compile(r"k_copy")
+
+
+def counter(path, pattern):
+    return [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if pattern.search(r["Kernel_Name"])]
 
 
 def traffic(fetch, write, cfetch, cwrite, copy_bytes, storage, out, command):
-    f, w = counter(fetch, "k_update"), counter(write, "k_update")
-    cf, cw = counter(cfetch, "k_copy"), counter(cwrite, "k_copy")
+    f, w = counter(fetch, UPDATE), counter(write, UPDATE)
+    cf, cw = counter(cfetch, COPY), counter(cwrite, COPY)
     copy_bytes = int(copy_bytes)
     ffac = sum(copy_bytes / (x * 1024) for x in cf) / len(cf)
     wfac = sum(copy_bytes / (x * 1024) for x in cw) / len(cw)

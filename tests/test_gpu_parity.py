@@ -115,6 +115,41 @@ def test_sod_walls_fp32(n):
     assert all(v < 1e-5 for v in err.values()), err
 
 
+@pytest.mark.parametrize("dims", [(37, 5, 3), (2, 3, 4), (1, 4, 3)])
+def test_noslip_walls_fp32(dims):
+    """Moving no-slip walls, adiabatic at x = 0 and isothermal at x = nx dx, on a
+    smooth random field; nx = 1 puts both walls on one cell."""
+    case = W.noslip_case(*dims, seed=41)
+    n = 100
+    log(f"case {case.name} steps {n} walls u {case.params['wall_u']} T {case.params['wall_T']}")
+    _, Qg = run_gpu(case, n)
+    Qo = run_oracle(case, n)
+    err = compare(Qg, Qo, case.params)
+    log(f"  rel L2 {err}")
+    assert all(v < 1e-5 for v in err.values()), err
+
+
+@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP16, 2e-3), (W.STORAGE_BF16, 1.6e-2)])
+def test_noslip_walls_compressed_storage(storage, bound):
+    case = W.noslip_case(37, 5, 3, seed=42)
+    n = 100
+    log(f"case {case.name} storage {storage} steps {n}")
+    _, Qg = run_gpu(case, n, storage=storage)
+    err = compare(Qg, run_oracle(case, n), case.params)
+    log(f"  rel L2 {err}")
+    assert all(v < bound for v in err.values()), err
+
+
+@pytest.mark.parametrize("storage", [W.STORAGE_FP32, W.STORAGE_FP16, W.STORAGE_BF16])
+@pytest.mark.parametrize("launch", [(64, 64, 0, False), (256, 1024, 3, True)])
+def test_noslip_launch_shapes_bitwise_equal(launch, storage):
+    case = W.noslip_case(37, 5, 3, seed=43)
+    log(f"case {case.name} launch {launch} storage {storage}")
+    _, Qa = run_gpu(case, 9, storage=storage)
+    _, Qb = run_gpu(case, 9, storage=storage, launch=launch)
+    assert np.array_equal(Qa, Qb)
+
+
 @pytest.mark.parametrize("N", [128, 256, 512, 1024])
 def test_becker_equilibrium_ends_fp32(N):
     case = W.becker(N, 4, 4)
@@ -194,6 +229,8 @@ _STEP_DIAG_CASES = {
                                          W.tgv(32).Q0, 0), W.STORAGE_FP16, None, 20, 10),
     "sod_walls_fp32": (lambda: W.sod(256, 4, 4), W.STORAGE_FP32, None, 60, 5),
     "becker_ends_fp16": (lambda: W.becker(128, 4, 4), W.STORAGE_FP16, None, 40, 5),
+    "noslip_fp32": (lambda: W.noslip_case(37, 5, 3, seed=44), W.STORAGE_FP32, None, 10, 5),
+    "noslip_bf16": (lambda: W.noslip_case(37, 5, 3, seed=44), W.STORAGE_BF16, None, 10, 5),
 }
 
 
