@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libcnsf.so")
 NCOMP, NVEL, NPOP = 14, 7, 98
 CNSF_OK, CNSF_E_INVALID, CNSF_E_NOMEM, CNSF_E_DEVICE, CNSF_E_STATE, CNSF_E_SIZE = range(6)
 CNSF_HOST, CNSF_DEVICE = 0, 1
+CNSF_BC_PERIODIC, CNSF_BC_WALL, CNSF_BC_DIRICHLET, CNSF_BC_NOSLIP = 0, 1, 2, 3
 CNSF_DIAG_SUMS, CNSF_DIAG_SPECTRAL = 0, 1
 
 D14 = C.c_double * NCOMP

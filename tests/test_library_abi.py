@@ -71,7 +71,7 @@ def test_params_default_and_bytes(cnsf):
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("dt", 0.0), ("dx", -1.0), ("gamma", 1.0), ("tau_R", 0.0), ("tau_q", -1.0),
     ("omega_min", 0.0), ("omega_min", 2.5), ("tau_base_override", 0.4), ("f_mu", -1.0),
-    ("visc_law", 7), ("bc_x", 5), ("storage", 3), ("C_sigma", -1.0), ("prandtl", 0.0),
+    ("visc_law", 7), ("bc_x", 4), ("bc_x", -1), ("storage", 3), ("C_sigma", -1.0), ("prandtl", 0.0),
 ])
 def test_invalid_parameters_rejected(cnsf, field, value):
     prm = W.tgv_params(16)
@@ -95,6 +95,28 @@ def test_subcharacteristic_bound_and_reference_state(cnsf):
     prm["C_sigma"], prm["mu0"] = 10.0, 0.0
     with pytest.raises(cnsf.CnsfError):
         cnsf.cnsf_required_bytes(cnsf.make_params(prm))
+
+
+@pytest.mark.parametrize("wall_u,wall_T", [
+    ([[0.1, 0.0, 0.0], [0.0, 0.0, 0.0]], [1.0, 1.0]),      # normal wall velocity
+    ([[0.0, 0.0, 0.0], [0.0, 0.0, -0.2]], [1.0, -1.0]),    # negative temperature
+    ([[0.0, float("nan"), 0.0], [0.0] * 3], [0.0, 0.0]),  # non-finite velocity
+    ([[0.0] * 3, [0.0] * 3], [float("inf"), 0.0]),         # non-finite temperature
+])
+def test_invalid_noslip_walls_rejected(cnsf, wall_u, wall_T):
+    prm = W.noslip_case(8, 4, 4).params
+    prm.update(wall_u=wall_u, wall_T=wall_T)
+    with pytest.raises(cnsf.CnsfError) as e:
+        cnsf.cnsf_required_bytes(cnsf.make_params(prm))
+    assert e.value.status == cnsf.CNSF_E_INVALID
+
+
+def test_noslip_wall_fields_reach_the_struct(cnsf):
+    prm = W.noslip_case(8, 4, 4).params
+    p = cnsf.make_params(prm)
+    assert p.bc_x == cnsf.CNSF_BC_NOSLIP == W.BC_NOSLIP
+    assert [list(p.wall_u[s]) for s in range(2)] == prm["wall_u"] and list(p.wall_T) == prm["wall_T"]
+    assert cnsf.cnsf_required_bytes(p) > 0
 
 
 def test_lattice_too_large_for_32bit_offsets(cnsf):
