@@ -57,11 +57,13 @@ def tgv_field_device(n, slab=16):
     return Q
 
 
-def load_lattice_tgv(cnsf, n, storage, Qdev):
+def load_lattice_tgv(cnsf, n, storage, Qdev, placed=True):
+    """The benchmark lattice: by default on the fastest of several probed
+    population arrays (Lattice.placed), else on one plain allocation."""
     import torch
     import workloads as W
     prm = W.tgv_params(n, storage=STORAGES[storage])
-    L = cnsf.Lattice(prm)
+    L = cnsf.Lattice.placed(prm) if placed else cnsf.Lattice(prm)
     t0 = time.perf_counter()
     L.set_state(Qdev)
     torch.cuda.synchronize()
@@ -84,21 +86,6 @@ def time_update(L, steps, warmup):
     wall = time.perf_counter() - t0
     per = [ev[s].elapsed_time(ev[s + 1]) for s in range(steps)]
     return float(np.mean(per)), float(np.min(per)), wall
-
-
-def second_allocation_ms(cnsf, L, prm, steps, warmup):
-    """The same state in a second, coexisting population array: HBM throughput of
-    this access pattern depends on where the driver places the array (the
-    allocations' speeds differ by up to 20% on MI355X), so the spread is shown
-    beside the headline figure."""
-    import torch
-    L2 = cnsf.Lattice(prm)
-    L2.buf.copy_(L.buf)
-    torch.cuda.synchronize()
-    ms = time_update(L2, steps, warmup)[0]
-    L2.close()
-    del L2
-    return ms
 
 
 SPECTRUM_BYTES_PER_CELL = {"fp32": 688, "fp16": 492, "bf16": 492}
@@ -258,7 +245,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-placement", action="store_true", help="skip the second-allocation timing")
+    ap.add_argument("--no-placement", action="store_true",
+                    help="one plain allocation per lattice instead of the fastest of several probed arrays")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the shell-spectrum timing")
     ap.add_argument("--no-walls", action="store_true", help="skip the no-slip wall timing")
     ap.add_argument("--copy-only", type=int, default=0, metavar="GIB",
@@ -282,7 +270,7 @@ def main():
 
     storages = list(STORAGES) if args.storage == "all" else [args.storage]
     head = "fp32" if "fp32" in storages else storages[0]
-    placement = None
+    placement = {}
     spectrum = None
     n = args.n
     Qdev = tgv_field_device(n)
@@ -290,13 +278,12 @@ def main():
     res = {}
     walls = {}
     for st in storages:
-        L, prm = load_lattice_tgv(cnsf, n, st, Qdev)
+        L, prm = load_lattice_tgv(cnsf, n, st, Qdev, placed=not args.no_placement)
         launch = L.get_launch()
-        if st == head and not args.no_placement:
-            placement = [None, second_allocation_ms(cnsf, L, prm, args.steps, args.warmup)]
+        if not args.no_placement:
+            placement[st] = dict(probe_ms=[round(x, 3) for x in L.placement_ms], kept=L.placement_kept)
+            log(f"  {st} placement probe: {placement[st]['probe_ms']} ms per update, kept #{L.placement_kept}")
         mean_ms, min_ms, wall = time_update(L, args.steps, args.warmup)
-        if st == head and not args.no_placement:
-            placement[0] = mean_ms
         if st == head and not args.no_spectrum:
             spectrum = spectrum_timing(L, st)
             spectrum["diagnostics_ms"] = diagnostics_timing(L)
@@ -359,9 +346,11 @@ def main():
     }
     if spectrum is not None:
         out["spectrum"] = dict(spectrum, storage=head)
-    if placement is not None:
-        out["placement"] = {"storage": head, "ms_per_step": [round(x, 4) for x in placement],
-                            "note": "same state in two coexisting allocations; value is the first"}
+    if placement:
+        out["placement"] = dict(placement, policy="each lattice on the fastest of up to 8 probed population arrays, "
+                                                  "as many as fit in 85% of free memory (Lattice.placed: 4 timed "
+                                                  "updates of the cleared state per candidate); value is the full "
+                                                  "timed run on the kept array")
     if walls:
         out["noslip_walls"] = dict(walls, note="no-slip x-walls (still adiabatic, moving isothermal): same state "
                                                "and population array as the periodic figure")

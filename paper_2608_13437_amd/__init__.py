@@ -288,6 +288,52 @@ class Lattice:
         self.h = cnsf_create(self.p, self.buf.data_ptr(), self.nbytes, _stream_handle(stream))
         self.shape = (self.p.nz, self.p.ny, self.p.nx)
 
+    @classmethod
+    def placed(cls, prm: dict, *, candidates: int | None = None, probe_steps: int = 4, device="cuda", stream=None):
+        """A lattice whose population array is the fastest of `candidates` allocations
+        (default: as many as fit in 85% of the free device memory, at most 8).
+
+        The same update runs at one of two speeds (about 20% apart on large
+        arrays) depending on the physical memory behind the array, and an
+        allocation keeps its speed for its lifetime.  Each candidate array is
+        created (cleared), timed over `probe_steps` updates of its cleared
+        state after one untimed update, and kept alive until all are timed, so
+        that each gets different memory; the fastest is kept and the others
+        freed.  The returned lattice is freshly created on that array (cleared,
+        step 0).  Candidates that no longer fit in memory are skipped.
+        ``placement_ms`` holds each candidate's mean time per update and
+        ``placement_kept`` the index kept."""
+        torch = _torch()
+        if candidates is None:
+            free = torch.cuda.mem_get_info(torch.device(device))[0]
+            candidates = min(8, int(0.85 * free) // max(1, cnsf_required_bytes(make_params(prm))))
+        lats, ms = [], []
+        for _ in range(max(1, int(candidates))):
+            try:
+                L = cls(prm, device=device, stream=stream)
+            except torch.cuda.OutOfMemoryError:
+                if not lats:
+                    raise
+                break
+            s = stream if stream is not None else torch.cuda.current_stream(L.device)
+            L.step(1)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            L.step(probe_steps)
+            b.record(s)
+            b.synchronize()
+            ms.append(a.elapsed_time(b) / probe_steps)
+            lats.append(L)
+        best = min(range(len(ms)), key=ms.__getitem__)
+        buf = lats[best].buf
+        for L in lats:
+            L.close()
+        del lats, L
+        torch.cuda.empty_cache()      # return the slower arrays to the device
+        out = cls(prm, device=device, stream=stream, buf=buf)
+        out.placement_ms, out.placement_kept = ms, best
+        return out
+
     def close(self):
         if getattr(self, "h", None):
             cnsf_destroy(self.h)

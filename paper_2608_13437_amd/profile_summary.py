@@ -27,6 +27,13 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def timed_launches(trace_path, count):
+    """Durations (ms) of the last `count` periodic update dispatches in a kernel trace."""
+    rows = [r for r in csv.DictReader(open(trace_path)) if UPDATE.search(r["Kernel_Name"])]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in rows[-count:]]
+
+
 def stats(path, out, command, bench_log=None):
     rows = list(csv.DictReader(open(path)))
     lines = [f"# rocprofv3 kernel statistics", f"# command: {command}", f"# kernel source hash: {kernel_hash()}"]
@@ -37,6 +44,13 @@ def stats(path, out, command, bench_log=None):
                 rec = json.loads(line)
                 lines.append(f"# bench.py in the same process: ms_per_step {rec['ms_per_step']} "
                              f"(mean of the even and odd launches), {rec['value']} {rec['unit']}")
+                trace = os.path.join(os.path.dirname(path), "run_kernel_trace.csv")
+                if os.path.exists(trace):
+                    # the table below also counts the placement probe's launches on
+                    # the candidate arrays; the timed region is the last `steps` ones
+                    d = timed_launches(trace, int(rec["steps"]))
+                    lines.append(f"# timed region in the kernel trace: last {len(d)} update launches, "
+                                 f"mean {sum(d) / len(d):.4f} ms (min {min(d):.4f}, max {max(d):.4f})")
     lines.append("")
     lines.append(f"{'calls':>6} {'avg_ms':>10} {'min_ms':>10} {'max_ms':>10} {'pct':>7}  kernel")
     for r in rows:

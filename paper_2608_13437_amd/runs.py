@@ -4,12 +4,17 @@ usage:
   python -m paper_2608_13437_amd.runs subsonic   [--n N] [--out PATH]
   python -m paper_2608_13437_amd.runs supersonic [--n N] [--f-mu F] [--t-end T] [--out PATH]
   python -m paper_2608_13437_amd.runs sweep      [--n N] [--f-mu F] [--C-sigma 10 20 40 80] [--out PATH]
+  python -m paper_2608_13437_amd.runs couette    [--n 16 32 64 128] [--t-end T] [--out PATH]
 
 * subsonic: the shock-free verification case of Section 3.2 (Re 500, M0 0.5,
   f_mu 0) to t_c = 10.
 * supersonic: the compressible case of Section 3.2 (Re 1600, M0 1.25, C_sigma 40,
   J_min 1e-2, omega_min 1.987) with the given f_mu.
 * sweep: the supersonic case once per sensor slope C_sigma.
+* couette: steady compressible Couette flow between no-slip isothermal walls
+  (one still, one moving at U = 0.5, Mach 0.42) at each resolution, against
+  its closed form: u = U x/H and T = T_w + (mu U^2 / 2 kappa) (x/H)(1 - x/H)
+  at uniform pressure, the steady state of Eq. (2) with constant viscosity.
 
 Every step and every diagnostic runs in the HIP library; inputs come from the
 seeded generators of ``workloads``.  A run that turns non-finite stops and
@@ -77,6 +82,37 @@ def tgv_run(n, *, t_end=None, steps=None, every=10, spectra_at=(), storage=W.STO
                 history=hist, spectra=spectra)
 
 
+def couette_run(n, *, U=0.5, T_w=1.0, mu=0.05, f_mu=None, t_end=30.0, storage=W.STORAGE_FP32, ny=4, nz=4):
+    """Couette flow from rest to t_end; errors of the final state against the closed
+    form.  f_mu defaults to 0.16/n, so the background dissipation vanishes under
+    refinement like the paper's resolution-dependent values."""
+    import numpy as np
+    f_mu = 0.16 / n if f_mu is None else f_mu
+    prm = W.couette_params(n, ny, nz, U=U, T_L=T_w, T_R=T_w, mu=mu, f_mu=f_mu)
+    prm["storage"] = storage
+    L = Lattice(prm)
+    sh = (nz, ny, n)
+    one, zero = np.ones(sh), np.zeros(sh)
+    L.set_state(W.conserved(one, zero, zero, zero, T_w * one, prm["gamma"]))
+    steps = int(round(t_end / prm["dt"]))
+    t0 = time.perf_counter()
+    L.step(steps)
+    P = L.primitives().mean(axis=(1, 2))
+    wall = time.perf_counter() - t0
+    L.step(100)
+    change = float(np.abs(L.primitives().mean(axis=(1, 2)) - P).max())
+    L.close()
+    g = prm["gamma"]
+    kappa = g * mu / ((g - 1.0) * prm["prandtl"])
+    x = (np.arange(n) + 0.5) / n
+    rise = mu * U * U / (2.0 * kappa)
+    u_e, T_e = U * x, T_w + rise * x * (1.0 - x)
+    return dict(n=n, f_mu=f_mu, dt=prm["dt"], steps=steps, wall_seconds=round(wall, 2),
+                err_u=float(np.abs(P[2] - u_e).max() / U), err_T=float(np.abs(P[5] - T_e).max() / (rise / 4.0)),
+                p_spread=float((P[4].max() - P[4].min()) / P[4].mean()), change_100_steps=change,
+                u=P[2].tolist(), T=P[5].tolist())
+
+
 def summary(run):
     h = run["history"]
     i = max(range(len(h["eps_s"])), key=lambda j: h["eps_s"][j])
@@ -87,8 +123,8 @@ def summary(run):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("case", choices=("subsonic", "supersonic", "sweep"))
-    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("case", choices=("subsonic", "supersonic", "sweep", "couette"))
+    ap.add_argument("--n", type=int, nargs="+", default=None)
     ap.add_argument("--f-mu", type=float, default=None)
     ap.add_argument("--C-sigma", type=float, nargs="+", default=[10.0, 20.0, 40.0, 80.0])
     ap.add_argument("--t-end", type=float, default=None)
@@ -96,15 +132,27 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     runs = []
+    if a.case == "couette":
+        for n in a.n or [16, 32, 64, 128]:
+            r = couette_run(n, t_end=a.t_end or 30.0, f_mu=a.f_mu)
+            print(f"couette n {n}: {r['steps']} steps, max |u - u_e|/U {r['err_u']:.3e}, max |T - T_e|/rise "
+                  f"{r['err_T']:.3e}, p spread {r['p_spread']:.2e}, change over 100 steps "
+                  f"{r['change_100_steps']:.1e}, {r['wall_seconds']} s", flush=True)
+            runs.append(r)
+        if a.out:
+            with open(a.out, "w") as fh:
+                json.dump(runs, fh)
+        return
+    n = (a.n or [128])[0]
     if a.case == "subsonic":
-        runs.append(tgv_run(a.n, t_end=a.t_end or 10.0, every=a.every, spectra_at=(0.0, 5.0, 10.0),
+        runs.append(tgv_run(n, t_end=a.t_end or 10.0, every=a.every, spectra_at=(0.0, 5.0, 10.0),
                             M0=0.5, Re=500.0, f_mu=0.0 if a.f_mu is None else a.f_mu))
     elif a.case == "supersonic":
-        runs.append(tgv_run(a.n, t_end=a.t_end or 20.0, every=a.every, spectra_at=(0.0, 9.0),
+        runs.append(tgv_run(n, t_end=a.t_end or 20.0, every=a.every, spectra_at=(0.0, 9.0),
                             f_mu=a.f_mu))
     else:
         for cs in a.C_sigma:
-            runs.append(tgv_run(a.n, t_end=a.t_end or 20.0, every=a.every, f_mu=a.f_mu, C_sigma=cs))
+            runs.append(tgv_run(n, t_end=a.t_end or 20.0, every=a.every, f_mu=a.f_mu, C_sigma=cs))
     for r in runs:
         print(summary(r), flush=True)
     if a.out:

@@ -50,3 +50,28 @@ def test_tgv_history_matches_oracle(golden, storage, bound):
     print(f"{golden} storage {storage}: history rel L2 {err}", flush=True)
     sys.stdout.flush()
     assert all(v < bound for v in err.values()), err
+
+
+@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP32, 1e-5), (W.STORAGE_FP16, 2e-3)])
+def test_couette_run_matches_oracle_steady_state(storage, bound):
+    """The run driver's Couette flow between no-slip walls (one moving, both
+    isothermal) against the oracle's state at the same time (written by
+    tests/golden/make_couette_steady.py): relative L2 of u_y and T within the
+    parity bound.  For FP32 populations the viscous temperature rise T - T_w
+    (about 6e-3, three orders below T) is also held to 100x the bound; FP16
+    deviations do not resolve it over 21,061 steps (23% off)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_13437_amd import runs
+    gold = json.load(open(os.path.join(GOLDEN, "couette16_steady.json")))
+    print(f"case couette{gold['n']} storage {storage} steps {gold['steps']}", flush=True)
+    r = runs.couette_run(gold["n"], U=gold["U"], mu=gold["mu"], f_mu=gold["f_mu"], t_end=gold["t_end"],
+                         storage=storage)
+    assert r["steps"] == gold["steps"]
+    e = dict(u_y=rel_l2(r["u"], gold["u_y"]), T=rel_l2(r["T"], gold["T"]),
+             rise=rel_l2(np.asarray(r["T"]) - 1.0, np.asarray(gold["T"]) - 1.0))
+    print(f"  rel L2 {e}; against the closed form: u {r['err_u']:.2e}, T {r['err_T']:.2e}", flush=True)
+    assert e["u_y"] < bound and e["T"] < bound, e
+    if storage == W.STORAGE_FP32:
+        assert e["rise"] < 100 * bound, e

@@ -327,6 +327,24 @@ def test_checkpoint_roundtrip_bitwise():
     assert B.info()[0] == 51 and B.info()[1] == 1
 
 
+def test_placed_lattice_behaves_as_plain_one():
+    """Lattice.placed probes candidate arrays, keeps one and re-creates the lattice
+    on it: cleared, step 0, and bitwise the same run as a plain lattice."""
+    cnsf = _cnsf()
+    case = W.random_case(13, 11, 9, seed=5, sensor=True, amp=0.5)
+    A = cnsf.Lattice.placed(case.params, candidates=2, probe_steps=2)
+    log(f"  probe ms {A.placement_ms} kept {A.placement_kept}")
+    assert len(A.placement_ms) == 2 and A.placement_kept in (0, 1)
+    assert A.info()[:2] == (0, 0)
+    B = cnsf.Lattice(case.params)
+    for L in (A, B):
+        L.set_state(case.Q0)
+        L.step(7)
+    assert np.array_equal(A.export_populations()[0], B.export_populations()[0])
+    A.close()
+    B.close()
+
+
 def test_set_state_rejects_nonphysical():
     cnsf = _cnsf()
     case = W.random_case(8, 8, 8, seed=7)
