@@ -27,11 +27,21 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def timed_launches(trace_path, count):
-    """Durations (ms) of the last `count` periodic update dispatches in a kernel trace."""
+PROBE_UPDATES = 5   # Lattice.placed: one untimed and four timed updates per candidate array
+
+
+def timed_launches(trace_path, rec):
+    """Durations (ms) of the periodic update dispatches of bench.py's timed region
+    (first storage): after the placement probe's updates on every candidate
+    array and the warmup updates, the next `steps` dispatches."""
     rows = [r for r in csv.DictReader(open(trace_path)) if UPDATE.search(r["Kernel_Name"])]
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in rows[-count:]]
+    placement = rec.get("placement") or {}
+    first = rec["config"]["storage"]
+    skip = PROBE_UPDATES * len(placement[first]["probe_ms"]) if first in placement else 0
+    skip += int(rec["warmup"])
+    sel = rows[skip:skip + int(rec["steps"])]
+    return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in sel]
 
 
 def stats(path, out, command, bench_log=None):
@@ -47,10 +57,11 @@ def stats(path, out, command, bench_log=None):
                 trace = os.path.join(os.path.dirname(path), "run_kernel_trace.csv")
                 if os.path.exists(trace):
                     # the table below also counts the placement probe's launches on
-                    # the candidate arrays; the timed region is the last `steps` ones
-                    d = timed_launches(trace, int(rec["steps"]))
-                    lines.append(f"# timed region in the kernel trace: last {len(d)} update launches, "
-                                 f"mean {sum(d) / len(d):.4f} ms (min {min(d):.4f}, max {max(d):.4f})")
+                    # the candidate arrays and any launches after the timed region
+                    d = timed_launches(trace, rec)
+                    lines.append(f"# timed region in the kernel trace: the {len(d)} update launches after the "
+                                 f"placement probe and warmup, mean {sum(d) / len(d):.4f} ms "
+                                 f"(min {min(d):.4f}, max {max(d):.4f})")
     lines.append("")
     lines.append(f"{'calls':>6} {'avg_ms':>10} {'min_ms':>10} {'max_ms':>10} {'pct':>7}  kernel")
     for r in rows:
