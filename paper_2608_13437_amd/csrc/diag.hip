@@ -20,6 +20,25 @@
 namespace cnsf {
 
 constexpr int DB = 256;  // threads per diagnostics block
+#ifndef CNSF_DERIV_PAIRS_X
+// Line pairs per block of the derivative passes, and the unroll of their
+// global loads and stores (512^3 FP32, HIP events, results bitwise equal):
+// two pairs along x (more blocks per CU; the lines are contiguous anyway) and
+// four along y and z (64-byte x-runs, three blocks per CU) take the nine
+// passes and the readout from 17.9 to 15.1 ms; three pairs (48-byte runs) or
+// nine to eleven (one block per CU) are slower.
+#define CNSF_DERIV_PAIRS_X 2   // line pairs per block of the x-axis derivative pass (0: as many as fit)
+#endif
+#ifndef CNSF_DERIV_PAIRS_YZ
+#define CNSF_DERIV_PAIRS_YZ 4  // line pairs per block of the y and z passes (0: as many as fit)
+#endif
+#ifndef CNSF_DERIV_LDS
+#define CNSF_DERIV_LDS 65536   // LDS bytes a derivative-pass block may use
+#endif
+#ifndef CNSF_DERIV_UNROLL
+#define CNSF_DERIV_UNROLL 4    // unroll of the derivative pass's global load and store loops
+#endif
+constexpr int kDerivUnroll = CNSF_DERIV_UNROLL;
 
 template <int ST, int BC>
 __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* __restrict__ pop, const Geom g,
@@ -228,6 +247,7 @@ __global__ void __launch_bounds__(DB) k_deriv_axis(const double* __restrict__ uc
     __syncthreads();
     // load (bit-reversed positions for the decimation-in-time transform);
     // along y and z, consecutive threads take consecutive line pairs
+#pragma unroll kDerivUnroll
     for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
       uint32_t pr, j;
       if (da.axis == 0) { pr = e / n; j = e % n; }
@@ -266,6 +286,7 @@ __global__ void __launch_bounds__(DB) k_deriv_axis(const double* __restrict__ uc
       }
       __syncthreads();
     }
+#pragma unroll kDerivUnroll
     for (uint32_t e = threadIdx.x; e < cnt * n; e += blockDim.x) {
       uint32_t pr, j;
       if (da.axis == 0) { pr = e / n; j = e % n; }
@@ -497,7 +518,9 @@ hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial
     // twiddle table (FFT) or the derivative kernel (direct), <= 64 KiB
     const uint32_t rows = da.log2n ? 1u : 2u;
     const uint32_t extra = da.log2n ? (da.n - 1) * 16u : (da.n + 2) * 8u;
-    uint32_t tp = (65536u - extra) / (rows * lds_line(da.n) * 16u);
+    uint32_t tp = ((uint32_t)CNSF_DERIV_LDS - extra) / (rows * lds_line(da.n) * 16u);
+    if (ps.a == 0 && CNSF_DERIV_PAIRS_X > 0 && (uint32_t)CNSF_DERIV_PAIRS_X < tp) tp = CNSF_DERIV_PAIRS_X;
+    if (ps.a != 0 && CNSF_DERIV_PAIRS_YZ > 0 && (uint32_t)CNSF_DERIV_PAIRS_YZ < tp) tp = CNSF_DERIV_PAIRS_YZ;
     da.pairs_per_block = tp < 1 ? 1 : (tp > 16 ? 16 : tp);
     da.axis = ps.a;
     da.init = ps.init;
