@@ -132,8 +132,7 @@ def noslip_timing(cnsf, L, n, storage, Qdev, steps, warmup):
     isothermal and moving at x = L) on the same state and in the same
     population array as the periodic timing, so both see one placement."""
     import workloads as W
-    prm = W.tgv_params(n, storage=STORAGES[storage])
-    prm.update(bc_x=W.BC_NOSLIP, wall_u=[[0.0, 0.0, 0.0], [0.0, 0.5, 0.0]], wall_T=[0.0, prm["T_ref"]])
+    prm = W.tgv_wall_params(n, storage=STORAGES[storage])
     Lw = cnsf.Lattice(prm, buf=L.buf)
     Lw.set_state(Qdev)
     ms = time_update(Lw, steps, warmup)[0]

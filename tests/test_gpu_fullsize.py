@@ -72,3 +72,40 @@ def test_tgv512_probes_match_oracle(storage, bound):
     d = L.diagnostics(spectral=False)
     assert d["nonfinite"] == 0
     L.close()
+
+
+WALL_GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "tgv512_wall_probes_100steps.npz")
+
+
+@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP32, 1e-5), (W.STORAGE_FP16, 2e-3)])
+def test_tgv512_wall_probes_match_oracle(storage, bound):
+    """The 512^3 Taylor-Green state between no-slip x-walls (the benchmark's walled
+    configuration), 100 steps, at probe cubes touching each wall; expected values
+    from tests/golden/make_tgv512_wall_probes.py (oracle only)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_13437_amd as cnsf
+    gold = np.load(WALL_GOLDEN)
+    steps, half = int(gold["steps"]), int(gold["half"])
+    prm = W.tgv_wall_params(N, storage=storage)
+    assert prm["dt"] == float(gold["dt"])
+    log(f"case tgv512 no-slip walls storage {storage} steps {steps} probes {gold['probes'].tolist()}")
+    L = cnsf.Lattice(prm)
+    for z0 in range(0, N, 64):
+        L.set_state(W.tgv_slab(prm, z0, z0 + 64), z0=z0)
+    L.step(steps)
+    got, ref = [], []
+    for (zc, yc, wall), Qo in zip(gold["probes"], gold["Q"]):
+        zs, ys = (np.arange(c - half, c + half) % N for c in (zc, yc))
+        xs = np.arange(2 * half) if wall == 0 else np.arange(N - 2 * half, N)
+        Qg = np.concatenate([L.moments(int(z), 1) for z in zs], axis=1)[:, :, ys][:, :, :, xs]
+        got.append(fields(Qg, prm))
+        ref.append(fields(Qo, prm))
+        log(f"  probe {(int(zc), int(yc), int(wall))}: rel L2 {rel_l2(got[-1], ref[-1])}")
+    pooled = rel_l2({k: np.concatenate([g[k].ravel() for g in got]) for k in got[0]},
+                    {k: np.concatenate([r[k].ravel() for r in ref]) for k in ref[0]})
+    log(f"  pooled over {len(got)} probes: {pooled}")
+    assert all(v < bound for v in pooled.values()), pooled
+    assert L.diagnostics(spectral=False)["nonfinite"] == 0
+    L.close()

@@ -224,6 +224,14 @@ def smooth_random_case(nx, ny, nz, seed=0, *, steps=100, modes=3, amp=0.2, senso
     return Case(f"smooth{nx}x{ny}x{nz}_s{seed}", prm, Q, steps)
 
 
+def tgv_wall_params(n, **kw):
+    """The Taylor-Green parameters with no-slip x-walls: still and adiabatic at
+    x = 0, isothermal at T_ref and moving at 0.5 along y at x = 2 pi."""
+    prm = tgv_params(n, **kw)
+    prm.update(bc_x=BC_NOSLIP, wall_u=[[0.0, 0.0, 0.0], [0.0, 0.5, 0.0]], wall_T=[0.0, prm["T_ref"]])
+    return prm
+
+
 def noslip_case(nx, ny, nz, seed=0, *, steps=100, amp=0.2, sensor=True,
                 wall_u=((0.0, 0.1, -0.05), (0.0, 0.2, 0.1)), wall_T=(0.0, 1.1)):
     """Smooth random field between no-slip walls at x = 0 and x = nx dx.
