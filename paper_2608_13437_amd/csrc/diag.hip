@@ -39,6 +39,15 @@ constexpr int DB = 256;  // threads per diagnostics block
 #define CNSF_DERIV_UNROLL 4    // unroll of the derivative pass's global load and store loops
 #endif
 constexpr int kDerivUnroll = CNSF_DERIV_UNROLL;
+#ifndef CNSF_SPEC_LINES_X
+// Complex lines per block of the spectrum's axis passes, for the same reason
+// as the derivative passes: 512^3, results bitwise equal, 28.3-29.1 ms with
+// six lines everywhere, 25.4 ms with three along x and four along y and z.
+#define CNSF_SPEC_LINES_X 3    // complex lines per block of the spectrum's x pass (0: as many as fit)
+#endif
+#ifndef CNSF_SPEC_LINES_YZ
+#define CNSF_SPEC_LINES_YZ 4   // complex lines per block of its y and z passes (0: as many as fit)
+#endif
 
 template <int ST, int BC>
 __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* __restrict__ pop, const Geom g,
@@ -555,7 +564,6 @@ hipError_t launch_spectrum(const Geom& g, double* fields, double* partial, doubl
   const uint32_t extra = log2n ? (n - 1) * 16u : 0u;   // twiddle table
   uint32_t tl = (65536u - extra) / (rows * lds_line(n) * 16u);
   tl = tl < 1 ? 1 : (tl > 16 ? 16 : tl);
-  const size_t lds = (size_t)rows * tl * lds_line(n) * sizeof(double2) + extra;
   const double n3 = (double)N;
   for (int c = 0; c < 3; ++c) {
     for (int a = 0; a < 3; ++a) {
@@ -563,13 +571,15 @@ hipError_t launch_spectrum(const Geom& g, double* fields, double* partial, doubl
       sa.n = n;
       sa.stride = strides[a];
       sa.nlines = (uint32_t)(N / n);
-      sa.lines_per_block = tl;
+      const uint32_t cap = a == 0 ? (uint32_t)CNSF_SPEC_LINES_X : (uint32_t)CNSF_SPEC_LINES_YZ;
+      sa.lines_per_block = (cap > 0 && cap < tl) ? cap : tl;
       sa.log2n = log2n;
       sa.axis = a;
       sa.mode = a;
       sa.accumulate = c > 0;
       sa.escale = 0.5 / (n3 * n3);
-      hipLaunchKernelGGL(k_spectrum_axis, dim3(DIAG_BLOCKS), dim3(DB), lds, s, fields + c * N, data, energy, g, sa);
+      const size_t lds_a = (size_t)rows * sa.lines_per_block * lds_line(n) * sizeof(double2) + extra;
+      hipLaunchKernelGGL(k_spectrum_axis, dim3(DIAG_BLOCKS), dim3(DB), lds_a, s, fields + c * N, data, energy, g, sa);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
