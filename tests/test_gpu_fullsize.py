@@ -109,3 +109,31 @@ def test_tgv512_wall_probes_match_oracle(storage, bound):
     assert all(v < bound for v in pooled.values()), pooled
     assert L.diagnostics(spectral=False)["nonfinite"] == 0
     L.close()
+
+
+def test_tgv512_fused_readout_at_start_matches_closed_forms():
+    """The fused step-and-readout at 512^3 in the benchmark's launch shape reports
+    the start level: E_k = 1/8, eps_s = (3/4) mu0 and eps_d = 0 (the Taylor-Green
+    start is divergence-free at uniform T), and it equals the separate readout of
+    the same level."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_13437_amd as cnsf
+    prm = W.tgv_params(N, storage=W.STORAGE_FP32)
+    log("case tgv512 fused readout at t = 0")
+    L = cnsf.Lattice(prm)
+    for z0 in range(0, N, 64):
+        L.set_state(W.tgv_slab(prm, z0, z0 + 64), z0=z0)
+    d = L.diagnostics(spectral=True)
+    e = L.step_diagnostics(1, spectral=True)
+    log(f"  readout {d}\n  fused   {e}")
+    assert L.info()[0] == 1 and e["step"] == 0
+    assert abs(e["E_k"] - 0.125) < 1e-7
+    assert abs(e["eps_s"] - 0.75 * prm["mu0"]) < 1e-8
+    assert abs(e["eps_d"]) < 1e-12
+    for k in ("mass", "energy", "E_k", "eps_s"):
+        assert abs(e[k] - d[k]) <= 1e-12 * abs(d[k]), k
+    for k in ("min_rho", "min_p", "sensor_fraction", "nonfinite"):
+        assert e[k] == d[k], k
+    L.close()
