@@ -107,6 +107,46 @@ def _collide_cell(fc, prm):
     return out
 
 
+def _noslip_return(Qc, prm, side, k, f_out):
+    """Population of component k returning into a cell from the no-slip wall on
+    its side 0 (x = 0) or 1 (x = nx dx), from the outgoing post-collision f_out
+    and the cell's pre-collision state Qc.  Written out per component from the
+    wall reading (a moving wall, isothermal at T_w > 0 or adiabatic): the
+    momentum takes the wall's velocity and an adiabatic wall's q_x is zero (both
+    anti-bounce-back); every other component returns with its normal flux at the
+    wall: tau_xy, tau_xz: -visc(T*) u_w; q_x: heat(T_w) T_w; E: -(tau_xy u_wy +
+    tau_xz u_wz) + q_x (the cell's q_x; zero on an adiabatic wall); the rest 0."""
+    g = prm["gamma"]
+    lam = prm["dx"] / prm["dt"]
+    uw = [float(v) for v in prm["wall_u"][side]]
+    Tw = float(prm["wall_T"][side])
+    rho = Qc[0]
+    u = [Qc[1] / rho, Qc[2] / rho, Qc[3] / rho]
+    T = (g - 1) * (Qc[4] - 0.5 * rho * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)) / rho
+    Tstar = Tw if Tw > 0 else T
+    mu = _mu(Tstar, prm)
+    visc = mu / prm["tau_R"]
+    kap = g * prm["mu0"] / ((g - 1) * prm["prandtl"])
+    heat = kap * (mu / prm["mu0"]) / prm["tau_q"]
+    w = WGT[1]
+    c_in = 1.0 if side == 0 else -1.0
+    if k in (1, 2, 3):
+        return -f_out + 2 * w * rho * uw[k - 1]
+    if k == 11 and Tw <= 0:
+        return -f_out
+    if k == 4:
+        Fx = -(Qc[8] * uw[1] + Qc[9] * uw[2]) + (Qc[11] if Tw > 0 else 0.0)
+    elif k == 8:
+        Fx = -visc * uw[1]
+    elif k == 9:
+        Fx = -visc * uw[2]
+    elif k == 11:
+        Fx = heat * Tstar
+    else:
+        Fx = 0.0
+    return f_out + 2 * w * c_in * Fx / (0.25 * lam)
+
+
 def run(Q0, prm, nsteps):
     """Brute-force run; Q0 (14, nz, ny, nx).  Returns f (14, 7, nz, ny, nx)."""
     nz, ny, nx = Q0.shape[1:]
@@ -148,6 +188,11 @@ def run(Q0, prm, nsteps):
                     # the link hits the wall and returns reversed, with the mirror sign
                     for k in range(14):
                         B[(z, y, x)][k][BACK[i]] = mirror[k] * post[k][i]
+                elif bc == 3:
+                    Qc = [sum(A[c][k][j] for j in range(7)) for k in range(14)]
+                    side = 0 if xd < 0 else 1
+                    for k in range(14):
+                        B[(z, y, x)][k][BACK[i]] = _noslip_return(Qc, prm, side, k, post[k][i])
                 else:
                     pass  # leaves the domain
         if bc == 2:

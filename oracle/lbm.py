@@ -53,7 +53,9 @@ this code, so no function here is left with parity unpinned):
   divergence of a prescribed field; with C_sigma = 0 the rate is plain BGK.
 * stream: brute force on 4^3 grids, fixed points, symmetry, the wall equal
   to the mirror-doubled periodic domain, y/z-uniform data equal to 1D.
-* wall_state and the no-slip links: a still adiabatic wall equals the domain
+* wall_state and the no-slip links: the loop transcription in oracle.brute,
+  which writes each component's wall term out by hand, agrees with the
+  declared flux evaluated at the wall state here; a still adiabatic wall equals the domain
   doubled with its point-inverted image; gas at rest, and gas moving with
   the walls, are fixed points; steady Couette flow is linear with
   tau_xy = mu U/H; steady conduction converges at second order to the

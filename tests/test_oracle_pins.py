@@ -231,13 +231,19 @@ def test_brute_force_4cubed_periodic(sensor):
     assert _rel(fa, fb) < 1e-12
 
 
-@pytest.mark.parametrize("bc", [W.BC_WALL, W.BC_DIRICHLET])
-def test_brute_force_x_boundaries(bc):
+@pytest.mark.parametrize("bc,wall_T", [(W.BC_WALL, None), (W.BC_DIRICHLET, None),
+                                       (W.BC_NOSLIP, [0.0, 1.1]), (W.BC_NOSLIP, [1.2, 0.0])])
+def test_brute_force_x_boundaries(bc, wall_T):
+    """The vectorised oracle against the loop transcription; for no-slip walls the
+    loop version writes each component's wall term out by hand, the vectorised
+    one evaluates the declared flux at the wall state."""
     c = W.random_case(5, 3, 2, seed=22, sensor=True)
     prm = dict(c.params)
     prm["bc_x"] = bc
     prm["Q_left"] = W.uniform_state(1.2, (0.3, 0.0, 0.0), 1.1, prm["gamma"])
     prm["Q_right"] = W.uniform_state(0.8, (0.2, 0.1, 0.0), 0.9, prm["gamma"])
+    prm["wall_u"] = [[0.0, 0.1, -0.2], [0.0, 0.05, 0.3]]
+    prm["wall_T"] = wall_T or [0.0, 0.0]
     n = 10
     fa = lbm.run(c.Q0, prm, n)
     fb = brute.run(c.Q0, prm, n)
