@@ -176,6 +176,15 @@ int cnsf_set_primitive(cnsf_lattice* lat, const double* P, int32_t z0, int32_t n
  * CNSF_E_DEVICE if a launch fails. */
 int cnsf_step(cnsf_lattice* lat, int64_t n);
 
+/* Time the update on this lattice's population array: one untimed update, then
+ * `steps` >= 1 timed ones (HIP events on the lattice's stream); *ms receives
+ * their mean time per update.  Synchronises the stream and advances the
+ * lattice by 1 + steps.  The same update runs at different speeds in
+ * different physical allocations of the array, and an allocation keeps its
+ * speed; an allocation policy probes candidate arrays with this and keeps the
+ * fastest.  Errors as cnsf_step. */
+int cnsf_probe_update_ms(cnsf_lattice* lat, int32_t steps, double* ms);
+
 /* Q_k = sum_i f_{k,i} (the zeroth moment, Section 2.2) of the current time
  * level for z-planes [z0, z0+nzs), written FP64 to out (host or device) as
  * [14][nzs][ny][nx].  CNSF_E_SIZE if the slab leaves the lattice. */

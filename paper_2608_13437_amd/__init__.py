@@ -91,6 +91,7 @@ def library():
             "cnsf_get_primitives": [vp, dp, i32, i32, i32],
             "cnsf_diagnostics": [vp, i32, C.POINTER(cnsf_diag)],
             "cnsf_step_diagnostics": [vp, i64, i32, C.POINTER(cnsf_diag)],
+            "cnsf_probe_update_ms": [vp, i32, C.POINTER(C.c_double)],
             "cnsf_spectrum_shells": [vp, C.POINTER(i32)],
             "cnsf_spectrum": [vp, dp, i32, i32],
             "cnsf_get_info": [vp, C.POINTER(i64), C.POINTER(i32), C.POINTER(sz)],
@@ -158,6 +159,12 @@ def cnsf_step(h, n: int):
 
 def cnsf_get_moments(h, out_ptr: int, z0: int, nzs: int, where: int):
     _check(library().cnsf_get_moments(h, C.cast(C.c_void_p(out_ptr), C.POINTER(C.c_double)), z0, nzs, where))
+
+
+def cnsf_probe_update_ms(h, steps: int) -> float:
+    ms = C.c_double()
+    _check(library().cnsf_probe_update_ms(h, steps, C.byref(ms)))
+    return ms.value
 
 
 def _diag_dict(d: cnsf_diag) -> dict:
@@ -320,14 +327,7 @@ class Lattice:
                 if not lats:
                     raise
                 break
-            s = stream if stream is not None else torch.cuda.current_stream(L.device)
-            L.step(1)
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(s)
-            L.step(probe_steps)
-            b.record(s)
-            b.synchronize()
-            ms.append(a.elapsed_time(b) / probe_steps)
+            ms.append(cnsf_probe_update_ms(L.h, probe_steps))
             lats.append(L)
         best = min(range(len(ms)), key=ms.__getitem__)
         buf = lats[best].buf

@@ -411,6 +411,29 @@ int cnsf_step(cnsf_lattice* L, int64_t n) {
   return CNSF_OK;
 }
 
+int cnsf_probe_update_ms(cnsf_lattice* L, int32_t steps, double* ms) {
+  if (!L || !ms) return fail(CNSF_E_INVALID, "NULL argument");
+  if (steps < 1) return fail(CNSF_E_INVALID, "steps = %d < 1", steps);
+  (void)hipSetDevice(L->device);
+  if (int r = cnsf_step(L, 1)) return r;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, L->stream);
+  int r = CNSF_OK;
+  if (e == hipSuccess) r = cnsf_step(L, steps);
+  if (e == hipSuccess && r == CNSF_OK) e = hipEventRecord(b, L->stream);
+  if (e == hipSuccess && r == CNSF_OK) e = hipEventSynchronize(b);
+  float t = 0.0f;
+  if (e == hipSuccess && r == CNSF_OK) e = hipEventElapsedTime(&t, a, b);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (r != CNSF_OK) return r;
+  if (e != hipSuccess) return hip_fail(e, "probe timing");
+  *ms = (double)t / steps;
+  return CNSF_OK;
+}
+
 int cnsf_set_state(cnsf_lattice* L, const double* Q, int32_t z0, int32_t nzs, int32_t where) {
   return set_state_impl(L, Q, z0, nzs, where, false);
 }

@@ -346,6 +346,11 @@ def test_placed_lattice_behaves_as_plain_one():
         L.set_state(case.Q0)
         L.step(7)
     assert np.array_equal(A.export_populations()[0], B.export_populations()[0])
+    assert all(m > 0 for m in A.placement_ms)
+    ms = cnsf.cnsf_probe_update_ms(B.h, 3)          # one untimed and three timed updates
+    assert ms > 0 and B.info()[0] == 7 + 4
+    with pytest.raises(cnsf.CnsfError):
+        cnsf.cnsf_probe_update_ms(B.h, 0)
     A.close()
     B.close()
 
