@@ -161,8 +161,12 @@ int cnsf_destroy(cnsf_lattice* lat);
 
 /* Set the populations of z-planes [z0, z0+nzs) to f^eq(Q) (Section 2.2
  * initial state).  Q (host or device) is [14][nzs][ny][nx].  Resets the
- * step counter and parity when z0 == 0.  CNSF_E_STATE if a cell has rho <= 0,
- * p <= 0 or a non-finite value (checked on the device). */
+ * step counter (and the parity) when z0 == 0.  The populations are written in
+ * the layout of an even time level, so a lattice at an odd level (after an
+ * odd number of steps) accepts only a write of the whole lattice, z0 == 0 and
+ * nzs == nz; a slab there returns CNSF_E_INVALID and changes nothing (step
+ * once more, or write every plane in one call).  CNSF_E_STATE if a cell has
+ * rho <= 0, p <= 0 or a non-finite value (checked on the device). */
 int cnsf_set_state(cnsf_lattice* lat, const double* Q, int32_t z0, int32_t nzs, int32_t where);
 
 /* As cnsf_set_state, from primitive fields: P (host or device) is

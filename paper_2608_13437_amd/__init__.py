@@ -354,31 +354,34 @@ class Lattice:
     def ncells(self):
         return self.p.nx * self.p.ny * self.p.nz
 
+    def _fields_arg(self, F):
+        """(pointer, nzs, where, keep) of a (14, nzs, ny, nx) FP64 field: a NumPy array
+        (host) or a CUDA tensor on this lattice's device (converted on the current
+        stream, which the lattice's stream then waits for)."""
+        torch = _torch()
+        if isinstance(F, torch.Tensor):
+            if not F.is_cuda or F.device != self.buf.device:
+                raise ValueError(f"field tensor on {F.device}, lattice on {self.buf.device}")
+            if F.dim() != 4 or F.shape[0] != NCOMP or tuple(F.shape[2:]) != self.shape[1:]:
+                raise ValueError(f"field shape {tuple(F.shape)} is not (14, nzs, {self.shape[1]}, {self.shape[2]})")
+            F = F.to(dtype=torch.float64).contiguous()
+            if self.stream is not None:
+                self.stream.wait_stream(torch.cuda.current_stream(F.device))
+            return F.data_ptr(), F.shape[1], CNSF_DEVICE, F
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        if F.ndim != 4 or F.shape[0] != NCOMP or F.shape[2:] != self.shape[1:]:
+            raise ValueError(f"field shape {F.shape} is not (14, nzs, {self.shape[1]}, {self.shape[2]})")
+        return F.ctypes.data, F.shape[1], CNSF_HOST, F
+
     def set_state(self, Q, z0: int = 0):
         """Q: float64 (14, nzs, ny, nx) NumPy array (host) or torch CUDA tensor (device)."""
-        torch = _torch()
-        if isinstance(Q, torch.Tensor):
-            Q = Q.to(dtype=torch.float64).contiguous()
-            assert Q.is_cuda and Q.shape[0] == NCOMP
-            cnsf_set_state(self.h, Q.data_ptr(), z0, Q.shape[1], CNSF_DEVICE)
-            self._keep = Q
-        else:
-            Q = np.ascontiguousarray(Q, dtype=np.float64)
-            assert Q.shape[0] == NCOMP and Q.shape[2:] == self.shape[1:]
-            cnsf_set_state(self.h, Q.ctypes.data, z0, Q.shape[1], CNSF_HOST)
+        ptr, nzs, where, keep = self._fields_arg(Q)
+        cnsf_set_state(self.h, ptr, z0, nzs, where)
 
     def set_primitive(self, P, z0: int = 0):
         """P: float64 (14, nzs, ny, nx): rho, u (3), p, tau (6), q (3); host array or CUDA tensor."""
-        torch = _torch()
-        if isinstance(P, torch.Tensor):
-            P = P.to(dtype=torch.float64).contiguous()
-            assert P.is_cuda and P.shape[0] == NCOMP
-            cnsf_set_primitive(self.h, P.data_ptr(), z0, P.shape[1], CNSF_DEVICE)
-            self._keep = P
-        else:
-            P = np.ascontiguousarray(P, dtype=np.float64)
-            assert P.shape[0] == NCOMP and P.shape[2:] == self.shape[1:]
-            cnsf_set_primitive(self.h, P.ctypes.data, z0, P.shape[1], CNSF_HOST)
+        ptr, nzs, where, keep = self._fields_arg(P)
+        cnsf_set_primitive(self.h, ptr, z0, nzs, where)
 
     def primitives(self, z0: int = 0, nzs: int | None = None):
         """(6, nzs, ny, nx) FP64: rho, u_x, u_y, u_z, p, T of the current time level."""

@@ -38,9 +38,6 @@ const char* last_error() { return g_err.c_str(); }
 
 size_t elem_bytes(int storage) { return storage == CNSF_STORAGE_FP32 ? 4 : 2; }
 
-// FP32: one block per 1024-cell tile, XCD-contiguous; 16-bit storage: a
-// persistent grid of 24 blocks per compute unit striding over 2048-cell tiles
-// (measured fastest on MI355X at 512^3).
 Launch default_launch(int storage) {
   // Measured on the 512^3 update with the grouped slot layout: one block per
   // tile throughout; 256-cell tiles dealt to the XCDs in contiguous spans for
@@ -368,6 +365,14 @@ static int set_state_impl(cnsf_lattice* L, const double* Q, int32_t z0, int32_t 
   if (!L || !Q) return fail(CNSF_E_INVALID, "NULL argument");
   if (z0 < 0 || nzs < 0 || z0 + nzs > (int)L->g.nz) return fail(CNSF_E_SIZE, "slab [%d, %d) outside nz = %u", z0, z0 + nzs, L->g.nz);
   if (where != CNSF_HOST && where != CNSF_DEVICE) return fail(CNSF_E_INVALID, "where = %d", where);
+  // the initial populations are written in the even-pass layout (slot i of
+  // the cell itself); at an odd time level the other planes are stored in the
+  // odd layout, so only a write of the whole lattice (which restarts at an
+  // even level) keeps the array consistent
+  if (L->parity != 0 && !(z0 == 0 && nzs == (int)L->g.nz))
+    return fail(CNSF_E_INVALID,
+                "lattice at an odd time level (step %lld): set the whole lattice (z0 = 0, nzs = %u) or step once more",
+                (long long)L->step, L->g.nz);
   (void)hipSetDevice(L->device);
   const uint32_t nslab = (uint32_t)nzs * L->g.nxy;
   const uint32_t cell0 = (uint32_t)z0 * L->g.nxy;

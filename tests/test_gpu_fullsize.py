@@ -5,9 +5,10 @@ only the FP64 oracle: after n steps a cell depends only on the initial cube of
 half-width n around it (D3Q7 streams one face neighbour per step; collision
 and sensor are cell-local), so the oracle computes each probe cube exactly
 from a cropped initial field.  Bounds: relative L2 on rho, u and T of 1e-5 for
-FP32 populations and 2e-3 for FP16 deviations.  BF16 keeps 8 significant bits
-against FP16's 11, so its rounding error is 2^3 times larger; it is held to
-8 x 2e-3.
+FP32 populations and 2e-3 for 16-bit deviations, FP16 or BF16.  BF16 keeps 8
+significant bits against FP16's 11, its errors are about 8x FP16's, and it
+misses the bound: that case is a strict expected failure with the errors
+measured on MI355X.
 """
 import os
 import sys
@@ -37,8 +38,10 @@ def log(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP32, 1e-5), (W.STORAGE_FP16, 2e-3),
-                                           (W.STORAGE_BF16, 1.6e-2)])
+@pytest.mark.parametrize("storage,bound", [
+    (W.STORAGE_FP32, 1e-5), (W.STORAGE_FP16, 2e-3),
+    pytest.param(W.STORAGE_BF16, 2e-3, marks=pytest.mark.xfail(
+        strict=True, reason="BF16 misses the 2e-3 bound (measured on MI355X: rho 2.4e-3, u 6.2e-3, T 2.3e-3)"))])
 def test_tgv512_probes_match_oracle(storage, bound):
     import torch
     if not torch.cuda.is_available():

@@ -2,17 +2,23 @@
 
 The golden histories are written by tests/golden/make_tgv_history.py, which
 runs only the oracle:
-* tgv64_fmu3.6_history.json: the supersonic case (M0 1.25, Re 1600) at 64^3
-  to t_c = 20 (f_mu 3.6; the paper's 1.8 blows up in the oracle itself);
+* tgv64_fmu1.8_M1.25_Re1600_const_history.json: the supersonic case (M0 1.25,
+  Re 1600) at 64^3 with the paper's f_mu = 1.8, to t_c = 20, with constant mu
+  (a temperature-dependent mu makes the declared system lose hyperbolicity
+  near local Mach 2 and the run stops at t_c = 7.5);
+* tgv64_fmu3.6_history.json: the same flow with mu ~ T^0.76 at twice that
+  background dissipation, which carries it to t_c = 20;
+* tgv128_fmu0.9_history.json: the supersonic case at 128^3 with the paper's
+  f_mu = 0.9 and mu ~ T^0.76, to t_c = 20 (present once its oracle run, a
+  few hours of CPU time, has been written);
 * tgv32_fmu0_M0.5_Re500_history.json: the subsonic verification case of
   Section 3.2 (M0 0.5, Re 500, f_mu 0) at 32^3 to t_c = 10.
 paper_2608_13437_amd.runs repeats each case on the GPU, with the diagnostics
 every 10 steps; the relative L2 error over the sampled history must stay
-within 1% for FP32 populations and 2% for FP16 deviations.  BF16 keeps 8
-significant bits against FP16's 11, so its rounding error is 2^3 times larger
-and it is held to 8 x 2%: the supersonic histories meet 2% in BF16 too, but
-the subsonic eps_d, a quantity three orders below eps_s in this nearly
-incompressible flow, carries a 9.6% BF16 error.
+within 1% for FP32 populations and 2% for 16-bit deviations, FP16 or BF16.
+BF16 keeps 8 significant bits against FP16's 11: the subsonic eps_d, three
+orders below eps_s in this nearly incompressible flow, carries a 9.6% BF16
+error, a strict expected failure.
 """
 import json
 import os
@@ -25,7 +31,12 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-CASES = ["tgv64_fmu3.6_history.json", "tgv32_fmu0_M0.5_Re500_history.json"]
+CASES = [c for c in ("tgv64_fmu1.8_M1.25_Re1600_const_history.json", "tgv64_fmu3.6_history.json",
+                     "tgv128_fmu0.9_history.json", "tgv32_fmu0_M0.5_Re500_history.json")
+         if os.path.exists(os.path.join(GOLDEN, c))]
+LAWS = {"power 0.76": "power", "Sutherland 0.4042": "sutherland", "constant": "const"}
+STORAGES = [(W.STORAGE_FP32, 0.01), (W.STORAGE_FP16, 0.02), (W.STORAGE_BF16, 0.02)]
+BF16_MISS = {"tgv32_fmu0_M0.5_Re500_history.json": "eps_s 1.6e-2, eps_d 9.6e-2"}
 
 
 def rel_l2(a, b):
@@ -33,8 +44,18 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("golden", CASES)
-@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP32, 0.01), (W.STORAGE_FP16, 0.02), (W.STORAGE_BF16, 0.16)])
+def _params():
+    out = []
+    for g in CASES:
+        for st, bound in STORAGES:
+            marks = []
+            if st == W.STORAGE_BF16 and g in BF16_MISS:
+                marks = [pytest.mark.xfail(strict=True, reason=f"BF16 misses 2% (MI355X: {BF16_MISS[g]})")]
+            out.append(pytest.param(g, st, bound, marks=marks, id=f"{g.split('_history')[0]}-{st}"))
+    return out
+
+
+@pytest.mark.parametrize("golden,storage,bound", _params())
 def test_tgv_history_matches_oracle(golden, storage, bound):
     import torch
     if not torch.cuda.is_available():
@@ -42,8 +63,9 @@ def test_tgv_history_matches_oracle(golden, storage, bound):
     from paper_2608_13437_amd import runs
     ref = json.load(open(os.path.join(GOLDEN, golden)))
     c = ref["case"]
+    print(f"case {golden} storage {storage} steps {ref['steps']}", flush=True)
     run = runs.tgv_run(c["n"], steps=ref["steps"], every=ref["every"], storage=storage,
-                       M0=c["M0"], Re=c["Re"], f_mu=c["f_mu"])
+                       M0=c["M0"], Re=c["Re"], f_mu=c["f_mu"], law=LAWS[c["law"]])
     assert abs(run["case"]["dt"] - c["dt"]) < 1e-15
     assert run["status"] == "ok" and run["history"]["step"] == ref["history"]["step"]
     err = {k: rel_l2(run["history"][k], ref["history"][k]) for k in ("E_k", "eps_s", "eps_d")}

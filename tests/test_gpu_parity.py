@@ -19,6 +19,17 @@ from oracle import lbm
 pytestmark = pytest.mark.gpu
 warnings.simplefilter("ignore", RuntimeWarning)
 
+# 16-bit deviation storage is held to 2e-3 relative L2 on rho, u and T after
+# 100 steps, FP16 or BF16 alike.  BF16 keeps 8 significant bits against FP16's
+# 11, and its errors are about 8x FP16's: it misses the bound.  Those cases are
+# strict expected failures, each with the errors measured on MI355X, so a BF16
+# encoding that meets the bound turns them into failures to be re-examined.
+BOUND_16BIT = 2e-3
+
+
+def bf16_miss(measured):
+    return pytest.mark.xfail(strict=True, reason=f"BF16 misses the 2e-3 bound (measured on MI355X: {measured})")
+
 
 def _cnsf():
     import torch
@@ -129,8 +140,10 @@ def test_noslip_walls_fp32(dims):
     assert all(v < 1e-5 for v in err.values()), err
 
 
-@pytest.mark.parametrize("storage,bound,scaled", [(W.STORAGE_FP16, 2e-3, False), (W.STORAGE_BF16, 1.6e-2, False),
-                                                  (W.STORAGE_FP16, 2e-3, True)])
+@pytest.mark.parametrize("storage,bound,scaled", [
+    (W.STORAGE_FP16, BOUND_16BIT, False),
+    pytest.param(W.STORAGE_BF16, BOUND_16BIT, False, marks=bf16_miss("u 2.3e-3")),
+    (W.STORAGE_FP16, BOUND_16BIT, True)])
 def test_noslip_walls_compressed_storage(storage, bound, scaled):
     """16-bit deviations between no-slip walls; `scaled` stores tau and q x 256, so
     the returned links are rescaled after the wall rule."""
@@ -384,6 +397,47 @@ def test_slab_set_state_and_moments():
     assert rel_l2(full, Qo) < 1e-6
 
 
+def test_slab_set_state_at_odd_level_is_rejected():
+    """After an odd number of steps the array holds the odd-pass layout; a slab
+    written in the even layout would mix the two, so the library refuses it
+    (and leaves the state alone), while a write of the whole lattice restarts
+    it at step 0 and equals a fresh lattice bit for bit."""
+    cnsf = _cnsf()
+    case = W.tgv(16)
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    L.step(1)
+    before = L.export_populations()[0]
+    for z0, nzs in ((4, 4), (0, 8)):
+        with pytest.raises(cnsf.CnsfError) as e:
+            L.set_state(case.Q0[:, z0:z0 + nzs], z0=z0)
+        assert e.value.status == cnsf.CNSF_E_INVALID
+    assert np.array_equal(L.export_populations()[0], before) and L.info()[:2] == (1, 1)
+    L.set_state(case.Q0)
+    assert L.info()[:2] == (0, 0)
+    fresh = cnsf.Lattice(case.params)
+    fresh.set_state(case.Q0)
+    assert np.array_equal(L.export_populations()[0], fresh.export_populations()[0])
+    L.step(2)              # an even level again: slabs are accepted
+    L.set_state(case.Q0[:, 4:8], z0=4)
+
+
+def test_device_field_shape_is_checked():
+    """A device tensor whose (ny, nx) differs from the lattice is refused before
+    the library reads it."""
+    import torch
+    cnsf = _cnsf()
+    case = W.tgv(16)
+    L = cnsf.Lattice(case.params)
+    bad = torch.ones((14, 4, 16, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        L.set_state(bad)
+    with pytest.raises(ValueError):
+        L.set_primitive(bad)
+    L.set_state(torch.from_numpy(case.Q0).cuda())
+    assert rel_l2(L.moments(), case.Q0) < 1e-6
+
+
 # ------------------------------------------------------------------ primitive fields
 def _primitive_fields(Q, prm):
     rho, u, _, p, _ = lbm.primitives(Q, prm)
@@ -487,8 +541,10 @@ def test_spectrum_rejects_non_cubic_lattice():
 
 
 # ------------------------------------------------------------------ compressed storage
-@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP16, 2e-3), (W.STORAGE_BF16, None)])
-def test_compressed_storage_error(storage, bound):
+@pytest.mark.parametrize("storage", [W.STORAGE_FP16,
+                                     pytest.param(W.STORAGE_BF16, marks=bf16_miss("rho 2.3e-3, u 5.5e-3, T 2.1e-3"))])
+def test_compressed_storage_error(storage):
+    """Taylor-Green 32^3, 100 steps: 16-bit deviations against the FP64 oracle."""
     case = W.tgv(32)
     n = 100
     log(f"case tgv32 storage {storage}")
@@ -496,12 +552,12 @@ def test_compressed_storage_error(storage, bound):
     Qo = run_oracle(case, n)
     err = compare(Qg, Qo, case.params)
     log(f"  storage {storage} rel L2 {err}")
-    assert all(np.isfinite(v) for v in err.values())
-    if bound is not None:
-        assert all(v < bound for v in err.values()), err
+    assert all(v < BOUND_16BIT for v in err.values()), err
 
 
-@pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP16, 2e-3), (W.STORAGE_BF16, 1.6e-2)])
+@pytest.mark.parametrize("storage,bound", [
+    (W.STORAGE_FP16, BOUND_16BIT),
+    pytest.param(W.STORAGE_BF16, BOUND_16BIT, marks=bf16_miss("u 5.5e-3, scaled or not"))])
 def test_scaled_storage_keeps_small_components(storage, bound):
     """Per-component storage scales (stress and heat flux stored x 256).  FP16: the
     small deviations of those components partly fall in the subnormal range,
