@@ -181,8 +181,11 @@ def copy_bandwidth(cnsf, nbytes=8 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(n=64, steps=48):
-    """The FP64 oracle (NumPy, single-threaded elementwise code) on a bounded sample."""
+def cpu_baseline(n=64, steps=48, tube_steps=500):
+    """The FP64 oracle (NumPy, single-threaded elementwise code) on a bounded sample:
+    Taylor-Green (the headline's flow, MLUPS) and, beside it, the two shock tubes
+    (Sod 256 cells and Becker 128 cells along x; the oracle runs the y/z-uniform
+    tubes on one cell row, bitwise the N x 4 x 4 result)."""
     import warnings
     warnings.simplefilter("ignore", RuntimeWarning)
     import workloads as W
@@ -194,8 +197,65 @@ def cpu_baseline(n=64, steps=48):
     for _ in range(steps):
         f = lbm.step(f, case.params)
     dt = time.perf_counter() - t0
+    tubes = {}
+    for name, c in (("sod256", W.sod(256, 1, 1)), ("becker128", W.becker(128, 1, 1))):
+        f = lbm.init_populations(c.Q0, c.params)
+        t1 = time.perf_counter()
+        for _ in range(tube_steps):
+            f = lbm.step(f, c.params)
+        tt = time.perf_counter() - t1
+        tubes[name] = dict(us_per_step=round(tt / tube_steps * 1e6, 1), steps=tube_steps,
+                           MLUPS=round(c.params["nx"] * tube_steps / tt / 1e6, 4))
     return dict(value=round(n ** 3 * steps / dt / 1e6, 4), unit="MLUPS", cores=1, kind="oracle",
-                sample=f"Taylor-Green {n}^3, {steps} steps of the FP64 NumPy oracle ({dt:.1f} s)")
+                host_cpus=os.cpu_count(),
+                sample=f"Taylor-Green {n}^3, {steps} steps of the FP64 NumPy oracle ({dt:.1f} s); one core of "
+                       f"{os.cpu_count()} (NumPy elementwise code is single-threaded)",
+                shock_tubes=tubes)
+
+
+def shock_tube_timing(cnsf, steps=2000, warmup=50):
+    """Sod 256 x 4 x 4 between parity walls and Becker N x 4 x 4 (N = 128 ... 1024)
+    with equilibrium ends, FP32: microseconds per step from HIP events around
+    `steps` launches on the lattice's stream.  These lattices hold 4k-16k
+    cells, so each update is one short launch: the figures are launch-bound."""
+    import torch
+    import workloads as W
+    out = {}
+    cases = [("sod256x4x4", W.sod(256, 4, 4))] + [(f"becker{n}x4x4", W.becker(n, 4, 4)) for n in (128, 256, 512, 1024)]
+    for name, c in cases:
+        L = cnsf.Lattice(c.params)
+        L.set_state(c.Q0)
+        L.step(warmup)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        L.step(steps)
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / steps
+        finite = L.diagnostics(spectral=False)["nonfinite"] == 0
+        out[name] = dict(cells=L.ncells, us_per_step=round(us, 2), MLUPS=round(L.ncells / us, 1), finite=finite)
+        L.close()
+    return out
+
+
+def placed_copy_bandwidth(cnsf, L, reps=5):
+    """The plain copy kernel between the two halves of a lattice's (placed) population
+    array: the attainable streaming rate of that physical memory.  Run after the
+    update timing; it overwrites the populations."""
+    import torch
+    half = (L.nbytes // 2) & ~255
+    base = L.buf.data_ptr()
+    s = torch.cuda.current_stream().cuda_stream
+    cnsf.cnsf_hbm_copy(base + half, base, half, s)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        cnsf.cnsf_hbm_copy(base + half, base, half, s)
+    b.record()
+    torch.cuda.synchronize()
+    return 2 * half / (a.elapsed_time(b) / reps * 1e-3) / 1e9
 
 
 def traffic_entry(storage, mean_ms):
@@ -210,16 +270,21 @@ def traffic_entry(storage, mean_ms):
     return rec.get("bytes_per_launch")
 
 
-def run_batch(cnsf, steps, warmup):
-    """Ensemble of 64 uneven Taylor-Green lattices (FP16 storage): graph replay vs per-member launches."""
+def run_batch(cnsf, steps, warmup, placed=True):
+    """Ensemble of 64 uneven Taylor-Green lattices (FP16 storage): graph replay vs
+    per-step launches vs per-member launches.  The population array is placed
+    like the single lattices (Batch.placed: the fastest of several probed
+    allocations); the first candidate's probe is the plain-allocation rate."""
     import torch
     import workloads as W
     cases = W.batch_ensemble(materialize=False)
-    B = cnsf.Batch([c.params for c in cases])
+    prms = [c.params for c in cases]
+    B = cnsf.Batch.placed(prms) if placed else cnsf.Batch(prms)
     for j, c in enumerate(cases):
         B.set_state(j, W.tgv_slab(c.params, 0, c.params["nz"]))
     B.autotune(os.path.join(tempfile.gettempdir(), "cnsf_batch_autotune.json"), steps_per_trial=10)
     out = {}
+    alg = 98 * 2 * 2 * B.ncells            # FP16: 98 populations read and written, 2 B each
     for name, mode in (("graph", 1), ("launch", 0), ("sequential", 2)):
         B.step(warmup, mode)
         torch.cuda.synchronize()
@@ -228,8 +293,16 @@ def run_batch(cnsf, steps, warmup):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[name] = round(B.ncells * steps / dt / 1e6, 1)
+        if name == "graph":
+            out["graph_GBps"] = round(alg * steps / dt / 1e9, 1)
+            out["graph_frac_peak"] = round(alg * steps / dt / 1e9 / PEAK_HBM_GBPS, 4)
     out["cells"] = B.ncells
     out["members"] = len(cases)
+    if placed:
+        ms = B.placement_ms
+        out["placement"] = dict(probe_ms=[round(x, 4) for x in ms], kept=B.placement_kept,
+                                first_draw_MLUPS=round(B.ncells / (ms[0] * 1e-3) / 1e6, 1))
+    out["launch"] = dict(zip(("block", "tile", "grid", "graph_steps"), B.get_launch()))
     B.close()
     return out
 
@@ -248,6 +321,7 @@ def main():
                     help="one plain allocation per lattice instead of the fastest of several probed arrays")
     ap.add_argument("--no-spectrum", action="store_true", help="skip the shell-spectrum timing")
     ap.add_argument("--no-walls", action="store_true", help="skip the no-slip wall timing")
+    ap.add_argument("--no-tubes", action="store_true", help="skip the Sod / Becker shock-tube timing")
     ap.add_argument("--copy-only", type=int, default=0, metavar="GIB",
                     help="only run the plain copy kernel on GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -276,6 +350,7 @@ def main():
     cells = n ** 3
     res = {}
     walls = {}
+    placed_copy = None
     for st in storages:
         L, prm = load_lattice_tgv(cnsf, n, st, Qdev, placed=not args.no_placement)
         launch = L.get_launch()
@@ -298,6 +373,9 @@ def main():
                              GBps=round(alg_bytes / (wms * 1e-3) / 1e9, 1), vs_periodic=round(mean_ms / wms, 4),
                              finite=wfin)
             log(f"  {st} no-slip walls: {wms:.3f} ms/step ({mean_ms / wms:.3f}x the periodic rate)")
+        if st == head and not args.no_copy:
+            placed_copy = placed_copy_bandwidth(cnsf, L)
+            log(f"  copy kernel inside the {st} population array: {placed_copy:.0f} GB/s")
         L.close()
         del L
         torch.cuda.empty_cache()
@@ -335,6 +413,7 @@ def main():
             "traffic": traffic,
         },
         "hbm_copy_GBps": copy_gbps,
+        "hbm_copy_placed_GBps": None if placed_copy is None else round(placed_copy, 1),
         "variants": {st: {"ms_per_step": round(v["ms"], 4), "MLUPS": round(v["mlups"], 1),
                           "GBps": round(v["gbps"], 1), "frac_peak": round(v["gbps"] / PEAK_HBM_GBPS, 4),
                           "speedup_vs_fp32": (round(res["fp32"]["ms"] / v["ms"], 3) if "fp32" in res else None),
@@ -346,6 +425,11 @@ def main():
     if spectrum is not None:
         out["spectrum"] = dict(spectrum, storage=head)
     if placement:
+        for st, pl in placement.items():
+            ms0 = pl["probe_ms"][0]
+            gb0 = 98 * 2 * BYTES_PER_POP[st] * cells / (ms0 * 1e-3) / 1e9
+            pl["first_draw"] = dict(ms_per_step=ms0, MLUPS=round(cells / (ms0 * 1e-3) / 1e6, 1),
+                                    GBps=round(gb0, 1), frac_peak=round(gb0 / PEAK_HBM_GBPS, 4))
         out["placement"] = dict(placement, policy="each lattice on the fastest of up to 8 probed population arrays, "
                                                   "as many as fit in 85% of free memory (Lattice.placed: 4 timed "
                                                   "updates of the cleared state per candidate); value is the full "
@@ -353,8 +437,10 @@ def main():
     if walls:
         out["noslip_walls"] = dict(walls, note="no-slip x-walls (still adiabatic, moving isothermal): same state "
                                                "and population array as the periodic figure")
+    if not args.no_tubes:
+        out["shock_tubes"] = shock_tube_timing(cnsf)
     if not args.no_batch:
-        out["batch"] = run_batch(cnsf, 20, 4)
+        out["batch"] = run_batch(cnsf, 20, 4, placed=not args.no_placement)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

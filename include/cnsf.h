@@ -281,6 +281,8 @@ int cnsf_batch_get_moments(cnsf_batch* b, int32_t j, double* out, int32_t where)
  * 64), cells per tile (multiple of block), persistent grid size in blocks
  * (0: one block per tile), and the number of steps captured per graph. */
 int cnsf_batch_set_launch(cnsf_batch* b, int32_t block, int32_t tile, int32_t grid, int32_t graph_steps);
+/* The batch's current launch shape (any output pointer may be NULL). */
+int cnsf_batch_get_launch(const cnsf_batch* b, int32_t* block, int32_t* tile, int32_t* grid, int32_t* graph_steps);
 /* Time candidate launch shapes with HIP events and keep the fastest; results
  * are cached in the JSON file `cache_path` (may be NULL) keyed by the batch's
  * shape signature. */

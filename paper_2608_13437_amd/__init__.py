@@ -107,6 +107,7 @@ def library():
             "cnsf_batch_step": [vp, i64, i32],
             "cnsf_batch_get_moments": [vp, i32, dp, i32],
             "cnsf_batch_set_launch": [vp, i32, i32, i32, i32],
+            "cnsf_batch_get_launch": [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)],
             "cnsf_batch_autotune": [vp, C.c_char_p, i32],
         }
         for name, args in sig.items():
@@ -483,6 +484,12 @@ def cnsf_batch_set_launch(h, block: int, tile: int, grid: int, graph_steps: int)
     _check(library().cnsf_batch_set_launch(h, block, tile, grid, graph_steps))
 
 
+def cnsf_batch_get_launch(h):
+    v = [C.c_int32() for _ in range(4)]
+    _check(library().cnsf_batch_get_launch(h, *[C.byref(x) for x in v]))
+    return tuple(x.value for x in v)
+
+
 def cnsf_batch_autotune(h, cache_path: str | None, steps_per_trial: int):
     _check(library().cnsf_batch_autotune(h, cache_path.encode() if cache_path else None, steps_per_trial))
 
@@ -492,13 +499,65 @@ class Batch:
 
     MODE_LAUNCH, MODE_GRAPH, MODE_SEQUENTIAL = 0, 1, 2
 
-    def __init__(self, prms, *, device="cuda", stream=None):
+    def __init__(self, prms, *, device="cuda", stream=None, buf=None):
+        """buf: optional uint8 CUDA tensor of at least the required bytes for the
+        members' populations (e.g. another batch's, whose state this one then
+        overwrites)."""
         torch = _torch()
         self.prms = [dict(p) for p in prms]
         self.ps = [make_params(p) for p in prms]
         self.nbytes = cnsf_batch_required_bytes(self.ps)
-        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=torch.device(device))
+        if buf is not None:
+            if buf.dtype != torch.uint8 or not buf.is_cuda or buf.numel() < self.nbytes or not buf.is_contiguous():
+                raise ValueError(f"buf must be a contiguous uint8 CUDA tensor of >= {self.nbytes} bytes")
+            self.buf = buf
+        else:
+            self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=torch.device(device))
+        self.stream = stream
         self.h = cnsf_batch_create(self.ps, self.buf.data_ptr(), self.nbytes, _stream_handle(stream))
+
+    @classmethod
+    def placed(cls, prms, *, candidates: int | None = None, probe_steps: int = 4, device="cuda", stream=None):
+        """A batch whose population array is the fastest of `candidates` allocations
+        (default: as many as fit in 85% of the free device memory, at most 8),
+        by the policy of Lattice.placed: each candidate batch is created
+        (cleared) and timed over `probe_steps` launch-per-step updates after one
+        untimed update (HIP events on the batch's stream); all stay alive until
+        every one is timed; the fastest array is kept and the returned batch is
+        freshly created on it (cleared, step 0).  ``placement_ms`` holds each
+        candidate's mean time per step and ``placement_kept`` the index kept."""
+        torch = _torch()
+        torch.cuda.empty_cache()
+        need = cnsf_batch_required_bytes([make_params(p) for p in prms])
+        if candidates is None:
+            free = torch.cuda.mem_get_info(torch.device(device))[0]
+            candidates = min(8, int(0.85 * free) // max(1, need))
+        bs, ms = [], []
+        s = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        for _ in range(max(1, int(candidates))):
+            try:
+                B = cls(prms, device=device, stream=stream)
+            except torch.cuda.OutOfMemoryError:
+                if not bs:
+                    raise
+                break
+            B.step(1, cls.MODE_LAUNCH)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            B.step(probe_steps, cls.MODE_LAUNCH)
+            b.record(s)
+            b.synchronize()
+            ms.append(a.elapsed_time(b) / probe_steps)
+            bs.append(B)
+        best = min(range(len(ms)), key=ms.__getitem__)
+        buf = bs[best].buf
+        for B in bs:
+            B.close()
+        del bs, B
+        torch.cuda.empty_cache()
+        out = cls(prms, device=device, stream=stream, buf=buf)
+        out.placement_ms, out.placement_kept = ms, best
+        return out
 
     def close(self):
         if getattr(self, "h", None):
@@ -530,6 +589,10 @@ class Batch:
 
     def set_launch(self, block=256, tile=256, grid=0, graph_steps=20):
         cnsf_batch_set_launch(self.h, block, tile, grid, graph_steps)
+
+    def get_launch(self):
+        """(block, tile, grid, graph_steps) of the batched update."""
+        return cnsf_batch_get_launch(self.h)
 
     def autotune(self, cache_path=None, steps_per_trial=10):
         cnsf_batch_autotune(self.h, cache_path, steps_per_trial)

@@ -290,6 +290,15 @@ int cnsf_batch_set_launch(cnsf_batch* b, int32_t block, int32_t tile, int32_t gr
   return CNSF_OK;
 }
 
+int cnsf_batch_get_launch(const cnsf_batch* b, int32_t* block, int32_t* tile, int32_t* grid, int32_t* graph_steps) {
+  if (!b) return fail(CNSF_E_INVALID, "batch is NULL");
+  if (block) *block = b->block;
+  if (tile) *tile = (int32_t)b->tile;
+  if (grid) *grid = b->grid;
+  if (graph_steps) *graph_steps = b->graph_steps;
+  return CNSF_OK;
+}
+
 int cnsf_batch_step(cnsf_batch* b, int64_t n, int32_t mode) {
   if (!b) return fail(CNSF_E_INVALID, "batch is NULL");
   if (n < 0 || mode < 0 || mode > 2) return fail(CNSF_E_INVALID, "n %lld, mode %d", (long long)n, mode);

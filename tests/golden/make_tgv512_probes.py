@@ -10,7 +10,9 @@ is exactly the full-domain oracle's.
 
 Probe centres are drawn with numpy.random.default_rng(13437); the first three
 are fixed (one wraps the periodic x boundary).  The output file is rewritten
-after each probe, so an interrupted run keeps the probes it finished.
+after each probe, so an interrupted run keeps the probes it finished, and a
+later run with more probes keeps the ones already in the file (same centres,
+same time step) and computes only the rest.
 
 usage: python tests/golden/make_tgv512_probes.py [NPROBES]
 """
@@ -61,8 +63,15 @@ def main():
     nprobes = int(sys.argv[1]) if len(sys.argv) > 1 else 8
     prm = W.tgv_params(N, storage=W.STORAGE_FP32)
     centres, values = [], []
+    want = probe_centres(nprobes)
+    if os.path.exists(OUT):
+        old = np.load(OUT)
+        have = [tuple(int(v) for v in c) for c in old["centres"]]
+        if float(old["dt"]) == prm["dt"] and have == want[:len(have)]:
+            centres, values = have, list(old["Q"])
+            print(f"keeping {len(have)} probes from {OUT}", flush=True)
     t0 = time.time()
-    for c in probe_centres(nprobes):
+    for c in want[len(centres):]:
         values.append(probe(prm, c))
         centres.append(c)
         np.savez(OUT, centres=np.array(centres, dtype=np.int64), Q=np.array(values), steps=STEPS, half=HALF,

@@ -181,6 +181,37 @@ def test_becker_equilibrium_ends_fp32(N):
     assert all(v < 1e-5 for v in err.values()), err
 
 
+def test_becker_steady_state_against_oracle_and_closed_form():
+    """The Becker configuration run to its steady state (t = 0.03; the 10-90%
+    thickness then changes by under 0.1%): N x 4 x 4 for N = 128 ... 1024 on the
+    GPU.  At N = 128 and 256 the steady density matches the FP64 oracle's
+    (1e-5 relative L2); the thickness excess over the closed-form Becker
+    profile (Section 3.1, Table "thickness") is positive and falls at least 2x
+    per halving of dx, as it does in the oracle."""
+    from oracle import exact
+    from paper_2608_13437_amd import runs
+    _cnsf()
+    wex = exact.becker_width()
+    ex = {}
+    for N in (128, 256, 512, 1024):
+        log(f"case becker{N}x4x4 to t = 0.03")
+        r = runs.becker_run(N, t_end=0.03)
+        c1 = W.becker(N, 1, 1)
+        rho = np.asarray(r["rho"])
+        ex[N] = exact.thickness(c1.meta["x"], rho, lo=1.0, hi=8.0 / 3.0) / wex - 1.0
+        log(f"  {r['steps']} steps, excess {ex[N]:.4e} (run driver {r['excess']:.4e}), {r['us_per_step']} us/step")
+        assert abs(r["records"][-1]["excess"] - r["records"][-5]["excess"]) < 1e-3
+        if N <= 256:
+            Qo = run_oracle(c1, r["steps"])
+            err = rel_l2(rho, Qo[0, 0, 0])
+            ex_o = exact.thickness(c1.meta["x"], Qo[0, 0, 0], lo=1.0, hi=8.0 / 3.0) / wex - 1.0
+            log(f"  oracle excess {ex_o:.4e}; rho rel L2 {err:.2e}")
+            assert err < 1e-5 and abs(ex[N] - ex_o) < 1e-3 * max(1.0, ex_o)
+    assert all(e > 0 for e in ex.values()), ex
+    for a, b in ((128, 256), (256, 512), (512, 1024)):
+        assert ex[a] / ex[b] > 2.0, ex
+
+
 @pytest.mark.parametrize("storage", [W.STORAGE_FP32, W.STORAGE_FP16, W.STORAGE_BF16])
 @pytest.mark.parametrize("launch", [(64, 64, 0, False), (128, 512, 0, True), (256, 256, 0, False),
                                     (256, 1024, 3, True), (192, 768, 2, False), (256, 2048, 0, True)])
