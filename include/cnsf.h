@@ -228,6 +228,25 @@ int cnsf_spectrum(cnsf_lattice* lat, double* E, int32_t nshells, int32_t where);
  * stream).  Errors as cnsf_step and cnsf_diagnostics. */
 int cnsf_step_diagnostics(cnsf_lattice* lat, int64_t n, int32_t flags, cnsf_diag* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * cnsf_step_diagnostics(lat, n, CNSF_DIAG_SUMS, out), with the per-block partial
+ * sums and the final result in a fixed library workspace of
+ * CNSF_STATIC_DIAG_PARTIALS + 1 partials (96 bytes each, about 0.8 MB) per GPU,
+ * held until the process ends, instead of lattice-owned memory.  Allocates
+ * nothing (no hipMalloc, no allocating library call); eps_s and eps_d are
+ * zero, as with CNSF_DIAG_SUMS.  The update that reduces the level at entry
+ * runs on at most CNSF_STATIC_DIAG_PARTIALS blocks (a persistent grid when the
+ * lattice's launch has more tiles); the populations are those of n plain steps
+ * and the sums agree with cnsf_step_diagnostics to rounding order (minima and
+ * counts exactly).  Every call on one GPU shares that GPU's workspace: calls
+ * that overlap on one GPU (from several host threads or streams) race and
+ * must be serialised by the caller.  Errors: CNSF_E_INVALID (NULL argument,
+ * n < 1), CNSF_E_SIZE if cnsf_set_launch set a persistent grid of more than
+ * CNSF_STATIC_DIAG_PARTIALS blocks, CNSF_E_DEVICE. */
+#define CNSF_STATIC_DIAG_PARTIALS 8192
+int cnsf_step_diagnostics_static(cnsf_lattice* lat, int64_t n, cnsf_diag* out);
+
 /* Step counter, parity and the byte size of an exported checkpoint. */
 int cnsf_get_info(const cnsf_lattice* lat, int64_t* step, int32_t* parity, size_t* checkpoint_bytes);
 

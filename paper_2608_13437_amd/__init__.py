@@ -91,6 +91,7 @@ def library():
             "cnsf_get_primitives": [vp, dp, i32, i32, i32],
             "cnsf_diagnostics": [vp, i32, C.POINTER(cnsf_diag)],
             "cnsf_step_diagnostics": [vp, i64, i32, C.POINTER(cnsf_diag)],
+            "cnsf_step_diagnostics_static": [vp, i64, C.POINTER(cnsf_diag)],
             "cnsf_probe_update_ms": [vp, i32, C.POINTER(C.c_double)],
             "cnsf_spectrum_shells": [vp, C.POINTER(i32)],
             "cnsf_spectrum": [vp, dp, i32, i32],
@@ -177,6 +178,12 @@ def _diag_dict(d: cnsf_diag) -> dict:
 def cnsf_step_diagnostics(h, n: int, flags: int) -> cnsf_diag:
     d = cnsf_diag()
     _check(library().cnsf_step_diagnostics(h, n, flags, C.byref(d)))
+    return d
+
+
+def cnsf_step_diagnostics_static(h, n: int) -> cnsf_diag:
+    d = cnsf_diag()
+    _check(library().cnsf_step_diagnostics_static(h, n, C.byref(d)))
     return d
 
 

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -589,6 +590,73 @@ int cnsf_step_diagnostics(cnsf_lattice* L, int64_t n, int32_t flags, cnsf_diag* 
   r.eps_s = r2.eps_s;
   r.eps_d = r2.eps_d;
   fill_diag(L, r, spectral, step0, d);
+  return CNSF_OK;
+}
+
+}  // extern "C"
+
+// Workspace of cnsf_step_diagnostics_static: the per-block partial sums of
+// the first update and, after them, the final result.  One copy per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel: it takes the device address of each GPU's copy once, with
+// hipGetSymbolAddress, and uses that.
+namespace {
+constexpr int STATIC_PARTIALS = CNSF_STATIC_DIAG_PARTIALS;
+static __device__ __align__(256) cnsf::DiagPartial scratch[STATIC_PARTIALS + 1];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+cnsf::DiagPartial* g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `dev` (which must be current).
+int static_scratch(int dev, cnsf::DiagPartial** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(CNSF_E_DEVICE, "device %d beyond the %d supported", dev, MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_dev[dev] = static_cast<cnsf::DiagPartial*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return CNSF_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int cnsf_step_diagnostics_static(cnsf_lattice* L, int64_t n, cnsf_diag* d) {
+  if (!L || !d) return fail(CNSF_E_INVALID, "NULL argument");
+  if (n < 1) return fail(CNSF_E_INVALID, "n = %lld < 1", (long long)n);
+  if (L->lc.grid > STATIC_PARTIALS)
+    return fail(CNSF_E_SIZE,
+                "persistent grid of %d blocks: the static workspace holds the partial sums of at most %d blocks",
+                L->lc.grid, STATIC_PARTIALS);
+  (void)hipSetDevice(L->device);
+  DiagPartial* sp = nullptr;
+  if (int r = static_scratch(L->device, &sp)) return r;
+  // the update that reduces the level at entry runs on at most STATIC_PARTIALS
+  // blocks (a persistent grid when the lattice has more tiles); the populations
+  // it writes do not depend on the launch shape
+  Launch lc = L->lc;
+  uint32_t nb = update_blocks(L->g, lc);
+  if (nb > (uint32_t)STATIC_PARTIALS) {
+    lc.grid = STATIC_PARTIALS;
+    nb = STATIC_PARTIALS;
+  }
+  const int64_t step0 = L->step;
+  hipError_t e = launch_update_diag(L->p.storage, L->pop, L->g, L->ph, L->cd, L->parity, lc, L->phd, sp, nullptr,
+                                    L->stream);
+  if (e != hipSuccess) return hip_fail(e, "fused diagnostic update");
+  L->parity ^= 1;
+  ++L->step;
+  e = launch_diag_final(sp, (int)nb, sp + STATIC_PARTIALS, L->stream);
+  if (e != hipSuccess) return hip_fail(e, "diagnostic reduction");
+  if (int r = cnsf_step(L, n - 1)) return r;
+  DiagPartial r{};
+  e = hipMemcpyAsync(&r, sp + STATIC_PARTIALS, sizeof r, hipMemcpyDeviceToHost, L->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+  if (e != hipSuccess) return hip_fail(e, "step_diagnostics_static");
+  fill_diag(L, r, false, step0, d);
   return CNSF_OK;
 }
 
