@@ -322,6 +322,8 @@ def main():
     ap.add_argument("--no-spectrum", action="store_true", help="skip the shell-spectrum timing")
     ap.add_argument("--no-walls", action="store_true", help="skip the no-slip wall timing")
     ap.add_argument("--no-tubes", action="store_true", help="skip the Sod / Becker shock-tube timing")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched ensemble (the line carries no headline value)")
     ap.add_argument("--copy-only", type=int, default=0, metavar="GIB",
                     help="only run the plain copy kernel on GIB GiB (counter calibration)")
     args = ap.parse_args()
@@ -339,6 +341,11 @@ def main():
         gbps = copy_bandwidth(cnsf, nbytes=args.copy_only << 30, reps=args.steps)
         print(json.dumps({"copy_bytes_per_launch": 2 * (args.copy_only << 30), "copy_GBps": round(gbps, 1),
                           "launches": args.steps + 1}), flush=True)
+        return
+
+    if args.batch_only:
+        print(json.dumps({"batch": run_batch(cnsf, args.steps, args.warmup, placed=not args.no_placement)}),
+              flush=True)
         return
 
     storages = list(STORAGES) if args.storage == "all" else [args.storage]

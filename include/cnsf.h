@@ -281,7 +281,7 @@ const char* cnsf_status_string(int status);
  */
 typedef struct cnsf_batch cnsf_batch;
 
-/* Create a batch of n members.  dev_buf / bytes as in cnsf_create (cleared the
+/* Create a batch of n members (1 <= n <= 65536).  dev_buf / bytes as in cnsf_create (cleared the
  * same way), sized by cnsf_batch_required_bytes (NULL: library-allocated). */
 int cnsf_batch_required_bytes(const cnsf_params* members, int32_t n, size_t* bytes);
 int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size_t bytes, void* stream,

@@ -3,8 +3,9 @@
 //
 // A descriptor table in device memory holds each member's geometry, constants
 // and population offset.  Each member's cells are cut into tiles of `tile`
-// cells; tile t belongs to the member whose prefix-summed first tile is the
-// largest one <= t (binary search, uniform per block).  With grid = 0 every
+// cells, numbered member after member (prefix sums of the tile counts); a
+// second table gives the member of every tile, so a block finds its member
+// with one load instead of a search over the prefix sums.  With grid = 0 every
 // tile gets its own block; with grid > 0 a fixed grid strides over the tiles
 // (persistent within a step).  Steps can be captured once into a HIP graph
 // and replayed.  Mode 2 launches the single-lattice update per member, the
@@ -38,18 +39,12 @@ struct Member {
 
 template <int ST, bool SC, int PAR>
 __global__ void __launch_bounds__(256) k_batch_update(typename Store<ST>::T* __restrict__ base,
-                                                      const Member* __restrict__ members, int nmembers,
+                                                      const Member* __restrict__ members,
+                                                      const uint16_t* __restrict__ tile_member,
                                                       uint32_t total_tiles, uint32_t tile) {
   constexpr int parity = PAR;
   for (uint32_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-    // member of tile t (uniform): last m with tile0 <= t
-    int lo = 0, hi = nmembers - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (members[mid].tile0 <= t) lo = mid;
-      else hi = mid - 1;
-    }
-    const Member& M = members[lo];
+    const Member& M = members[tile_member[t]];   // uniform per block
     const Geom g = M.g;
     typename Store<ST>::T* pop = base + M.pop_offset;
     const uint32_t first = (t - M.tile0) * tile;
@@ -67,17 +62,18 @@ __global__ void __launch_bounds__(256) k_batch_update(typename Store<ST>::T* __r
   }
 }
 
-static hipError_t launch_batch(int storage, bool scaled, void* base, const Member* members, int n,
-                               uint32_t total_tiles, uint32_t tile, int block, int grid, int parity, hipStream_t s) {
+static hipError_t launch_batch(int storage, bool scaled, void* base, const Member* members,
+                               const uint16_t* tile_member, uint32_t total_tiles, uint32_t tile, int block, int grid,
+                               int parity, hipStream_t s) {
   const uint32_t nb = grid > 0 ? (uint32_t)grid : total_tiles;
 #define CNSF_CASE(ST, SC, T)                                                                            \
   if (storage == ST && scaled == SC) {                                                                  \
     if (parity)                                                                                         \
-      hipLaunchKernelGGL((k_batch_update<ST, SC, 1>), dim3(nb), dim3(block), 0, s, (T*)base, members, n, \
-                         total_tiles, tile);                                                            \
+      hipLaunchKernelGGL((k_batch_update<ST, SC, 1>), dim3(nb), dim3(block), 0, s, (T*)base, members,    \
+                         tile_member, total_tiles, tile);                                               \
     else                                                                                                \
-      hipLaunchKernelGGL((k_batch_update<ST, SC, 0>), dim3(nb), dim3(block), 0, s, (T*)base, members, n, \
-                         total_tiles, tile);                                                            \
+      hipLaunchKernelGGL((k_batch_update<ST, SC, 0>), dim3(nb), dim3(block), 0, s, (T*)base, members,    \
+                         tile_member, total_tiles, tile);                                               \
     return hipGetLastError();                                                                           \
   }
   CNSF_CASE(0, false, float)
@@ -98,6 +94,8 @@ struct cnsf_batch {
   std::vector<Member> m;   // host copy
   std::vector<PhysD> phd;
   Member* dm = nullptr;    // device table
+  uint16_t* dtile = nullptr;       // member of every tile (device)
+  uint32_t dtile_cap = 0;
   int storage = 0;
   void* base = nullptr;
   bool owned = false;
@@ -125,13 +123,26 @@ static void batch_drop_graph(cnsf_batch* b) {
 
 static int batch_retile(cnsf_batch* b) {
   uint32_t t0 = 0;
-  for (auto& M : b->m) {
+  std::vector<uint16_t> owner;
+  for (size_t j = 0; j < b->m.size(); ++j) {
+    Member& M = b->m[j];
     M.tile0 = t0;
     M.ntiles = (M.g.ncells + b->tile - 1) / b->tile;
     t0 += M.ntiles;
+    owner.insert(owner.end(), M.ntiles, (uint16_t)j);
   }
   b->total_tiles = t0;
-  hipError_t e = hipMemcpy(b->dm, b->m.data(), sizeof(Member) * b->m.size(), hipMemcpyHostToDevice);
+  hipError_t e = hipSuccess;
+  if (b->dtile_cap < t0) {
+    if (b->dtile) (void)hipFree(b->dtile);
+    b->dtile = nullptr;
+    b->dtile_cap = 0;
+    e = hipMalloc(&b->dtile, sizeof(uint16_t) * t0);
+    if (e != hipSuccess) return fail(CNSF_E_NOMEM, "tile table: %s", hipGetErrorString(e));
+    b->dtile_cap = t0;
+  }
+  e = hipMemcpy(b->dtile, owner.data(), sizeof(uint16_t) * t0, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->dm, b->m.data(), sizeof(Member) * b->m.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "descriptor upload");
   batch_drop_graph(b);
   return CNSF_OK;
@@ -139,7 +150,7 @@ static int batch_retile(cnsf_batch* b) {
 
 static hipError_t batch_launch_steps(cnsf_batch* b, int64_t n, hipStream_t s, int& parity) {
   for (int64_t i = 0; i < n; ++i) {
-    hipError_t e = launch_batch(b->storage, b->scaled, b->base, b->dm, (int)b->m.size(), b->total_tiles, b->tile,
+    hipError_t e = launch_batch(b->storage, b->scaled, b->base, b->dm, b->dtile, b->total_tiles, b->tile,
                                 b->block, b->grid, parity, s);
     if (e != hipSuccess) return e;
     parity ^= 1;
@@ -151,6 +162,7 @@ extern "C" {
 
 int cnsf_batch_required_bytes(const cnsf_params* members, int32_t n, size_t* bytes) {
   if (!members || n < 1 || !bytes) return fail(CNSF_E_INVALID, "batch needs n >= 1 members");
+  if (n > 65536) return fail(CNSF_E_INVALID, "%d members: a batch holds at most 65536", n);
   size_t tot = 0;
   for (int j = 0; j < n; ++j) {
     size_t nb = 0;
@@ -236,6 +248,7 @@ int cnsf_batch_destroy(cnsf_batch* b) {
   batch_drop_graph(b);
   if (b->owned && b->base) (void)hipFree(b->base);
   if (b->dm) (void)hipFree(b->dm);
+  if (b->dtile) (void)hipFree(b->dtile);
   if (b->dflag) (void)hipFree(b->dflag);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);

@@ -160,18 +160,25 @@ __global__ void k_moments(const typename Store<ST>::T* __restrict__ pop, double*
   }
 }
 
-// Plain copy, 4 x 16 bytes in flight per thread per iteration.
-__global__ void __launch_bounds__(256) k_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, uint64_t n16) {
+// Plain copy, 4 x 16 bytes in flight per thread per iteration, non-temporal
+// loads and stores (the copy's data is touched once).  Of the variants measured
+// on a 26 GB copy inside a fast 52.6 GB allocation on MI355X (1, 4 or 8 vectors
+// per thread, temporal or not, grid-strided or block-contiguous, 8 to 64 blocks
+// per compute unit) this one, at 64 blocks per unit, moves the most: 6.33 TB/s
+// against 5.92 TB/s for temporal accesses.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, uint64_t n16) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (; i + 3 * stride < n16; i += 4 * stride) {
-    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-    dst[i] = a;
-    dst[i + stride] = b;
-    dst[i + 2 * stride] = c;
-    dst[i + 3 * stride] = d;
+    const u32x4 a = __builtin_nontemporal_load(&src[i]), b = __builtin_nontemporal_load(&src[i + stride]);
+    const u32x4 c = __builtin_nontemporal_load(&src[i + 2 * stride]), d = __builtin_nontemporal_load(&src[i + 3 * stride]);
+    __builtin_nontemporal_store(a, &dst[i]);
+    __builtin_nontemporal_store(b, &dst[i + stride]);
+    __builtin_nontemporal_store(c, &dst[i + 2 * stride]);
+    __builtin_nontemporal_store(d, &dst[i + 3 * stride]);
   }
-  for (; i < n16; i += stride) dst[i] = src[i];
+  for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(&src[i]), &dst[i]);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -294,8 +301,8 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t s) 
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const uint64_t want = (n16 + 255) / 256;
-  const uint32_t nb = (uint32_t)(want < (uint64_t)ncu * 32 ? (want ? want : 1) : (uint64_t)ncu * 32);
-  hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, (const uint4*)src, (uint4*)dst, n16);
+  const uint32_t nb = (uint32_t)(want < (uint64_t)ncu * 64 ? (want ? want : 1) : (uint64_t)ncu * 64);
+  hipLaunchKernelGGL(k_copy, dim3(nb), dim3(256), 0, s, (const u32x4*)src, (u32x4*)dst, n16);
   return hipGetLastError();
 }
 

@@ -49,13 +49,15 @@ HISTORY_KEYS = ("E_k", "eps_s", "eps_d", "mass", "energy", "min_rho", "min_p", "
 
 
 def tgv_run(n, *, t_end=None, steps=None, every=10, spectra_at=(), storage=W.STORAGE_FP32, slab=32, progress=0,
-            **tgv_kw):
+            placed=False, **tgv_kw):
     """Run the Taylor-Green vortex on an n^3 lattice to t_end (convective times; or
     for `steps` steps, a multiple of `every`), recording the FP64 diagnostics every
     `every` steps and the shell spectrum at the recorded steps nearest to each
-    time in `spectra_at`.  progress > 0 prints a line every `progress` steps."""
+    time in `spectra_at`.  progress > 0 prints a line every `progress` steps;
+    placed puts the populations on the fastest of several probed allocations
+    (Lattice.placed), which only changes the speed."""
     prm = W.tgv_params(n, storage=storage, **tgv_kw)
-    L = Lattice(prm)
+    L = Lattice.placed(prm) if placed else Lattice(prm)
     for z0 in range(0, n, slab):
         L.set_state(W.tgv_slab(prm, z0, min(n, z0 + slab)), z0=z0)
     dt = prm["dt"]
@@ -212,6 +214,8 @@ def main(argv=None):
                     help="viscosity law of the Taylor-Green runs (mu ~ T^0.76, Sutherland, or constant)")
     ap.add_argument("--storage", choices=("fp32", "fp16", "bf16"), default="fp32")
     ap.add_argument("--progress", type=int, default=1000, help="print a line every this many steps")
+    ap.add_argument("--no-placement", action="store_true",
+                    help="one plain allocation instead of the fastest of several probed ones")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     runs = []
@@ -239,7 +243,7 @@ def main(argv=None):
         return
     n = (a.n or [128])[0]
     st = {"fp32": W.STORAGE_FP32, "fp16": W.STORAGE_FP16, "bf16": W.STORAGE_BF16}[a.storage]
-    kw = dict(every=a.every, law=a.law, storage=st, progress=a.progress)
+    kw = dict(every=a.every, law=a.law, storage=st, progress=a.progress, placed=not a.no_placement)
     if a.case == "subsonic":
         runs.append(tgv_run(n, t_end=a.t_end or 10.0, spectra_at=(0.0, 5.0, 10.0),
                             M0=0.5, Re=500.0, f_mu=0.0 if a.f_mu is None else a.f_mu, **kw))

@@ -272,6 +272,11 @@ def couette_params(n, ny=1, nz=1, *, U=0.02, T_L=1.0, T_R=1.0, mu=0.05, Pr=0.71,
 # --------------------------------------------------------------------------
 # Taylor-Green vortex (Section 3.2 and Eq. (7)); periodic [0, 2 pi)^3
 # --------------------------------------------------------------------------
+# Background dissipation f_mu of Section 3.2 per grid.  With a temperature-
+# dependent viscosity the declared system loses hyperbolicity near local Mach 2,
+# and at these values the 64^3, 256^3 and 512^3 runs turn non-finite near
+# t_c = 5.7-7.5 (128^3 reaches t_c = 20); with constant viscosity (law="const")
+# all of them reach t_c = 20.  The values are kept as the paper states them.
 TGV_DEFAULT_FMU = {64: 1.8, 128: 0.9, 256: 1e-2, 384: 1e-2, 512: 1e-2}
 
 
