@@ -234,6 +234,8 @@ Geom derive_geom(const cnsf_params* p, const PhysD& ph) {
 
 }  // namespace cnsf
 
+constexpr int STEP_FINAL_CHUNKS = 1024;   // chunk sums of the fused diagnostic step's final reduction
+
 struct cnsf_lattice {
   cnsf_params p;
   Geom g;
@@ -556,7 +558,8 @@ int cnsf_step_diagnostics(cnsf_lattice* L, int64_t n, int32_t flags, cnsf_diag* 
     if (L->step_partials) (void)hipFree(L->step_partials);
     L->step_partials = nullptr;
     L->step_partials_cap = 0;
-    e = hipMalloc(&L->step_partials, (size_t)nb * sizeof(DiagPartial));
+    // the block partials, then room for the chunk sums of the two-level final reduction
+    e = hipMalloc(&L->step_partials, (size_t)(nb + STEP_FINAL_CHUNKS) * sizeof(DiagPartial));
     if (e != hipSuccess) {
       L->step_partials = nullptr;
       return fail(CNSF_E_NOMEM, "step partials: %s", hipGetErrorString(e));
@@ -578,7 +581,8 @@ int cnsf_step_diagnostics(cnsf_lattice* L, int64_t n, int32_t flags, cnsf_diag* 
   L->parity ^= 1;
   ++L->step;
   if (spectral) e = launch_spectral(L->g, L->p.dx, L->fields, L->partials, true, L->stream);
-  if (e == hipSuccess) e = launch_diag_final(L->step_partials, (int)nb, L->dresult, L->stream);
+  if (e == hipSuccess)
+    e = launch_diag_final2(L->step_partials, (int)nb, L->step_partials + nb, STEP_FINAL_CHUNKS, L->dresult, L->stream);
   if (e == hipSuccess && spectral) e = launch_diag_final(L->partials, DIAG_BLOCKS, L->dresult2, L->stream);
   if (e != hipSuccess) return hip_fail(e, "diagnostic reductions");
   if (int r = cnsf_step(L, n - 1)) return r;

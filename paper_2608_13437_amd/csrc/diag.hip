@@ -11,6 +11,7 @@
 // transformed back; derivatives accumulate into div u and curl u.  The last
 // axis also reduces mu |curl u|^2 and mu (div u)^2 into the block partials.
 // Pass 5 reduces the block partials in a fixed order (deterministic).
+#include <algorithm>
 #include <cmath>
 
 #include "cnsf_impl.h"
@@ -39,6 +40,9 @@ constexpr int DB = 256;  // threads per diagnostics block
 #define CNSF_DERIV_UNROLL 4    // unroll of the derivative pass's global load and store loops
 #endif
 constexpr int kDerivUnroll = CNSF_DERIV_UNROLL;
+#ifndef CNSF_DERIV_512
+#define CNSF_DERIV_512 1       // 512-point lines take the register transform (k_deriv512)
+#endif
 #ifndef CNSF_SPEC_LINES_X
 // Complex lines per block of the spectrum's axis passes, for the same reason
 // as the derivative passes: 512^3, results bitwise equal, 28.3-29.1 ms with
@@ -85,6 +89,9 @@ struct DerivAxis {
   uint32_t log2n;           // 0 if n is not a power of two
   int axis;                 // 0 x, 1 y, 2 z
   int init;                 // store into the accumulator instead of adding
+  int eps;                  // k_deriv512 only: 0 store the result; 1, 2 reduce the eps sums of the
+                            // completed fields instead (1 into the eps fields of the partials,
+                            // 2 whole partials with the other fields neutral)
   double sign;
   double kscale;            // 2 pi / (n dx)
 };
@@ -313,6 +320,254 @@ __global__ void __launch_bounds__(DB) k_deriv_axis(const double* __restrict__ uc
   }
 }
 
+// ------------------------------------------------------------------ 512-point lines
+// Lines of 512 points (the 512^3 box) take a transform held in registers: one
+// wavefront per line pair, eight values per lane, three radix-8 steps with
+// two exchanges through the wave's own LDS slice (512 = 8 x 8 x 8), forward
+// from natural order to digit-reversed order and the inverse back.  With
+// j = t + 64 m (t the lane) and k = k2 + 8 k1 + 64 k0:
+//   step 1: lane t sums over m (radix 8), twiddle w^(t k2);
+//   step 2: lane (t mod 8, k2) sums over t div 8, twiddle w^(8 (t mod 8) k1);
+//   step 3: lane (k1, k2) sums over t mod 8 and holds Z[k2 + 8 k1 + 64 k0].
+// The inverse runs the same steps backwards with conjugate twiddles.
+constexpr uint32_t L512_ROW = 65;                 // exchange row: 64 values and one pad
+constexpr uint32_t L512_WAVE = 8 * L512_ROW;      // complex values per wave slice
+
+__device__ inline double2 mul_j(double2 a, int S) {   // a * exp(S i pi / 2)
+  return S < 0 ? make_double2(a.y, -a.x) : make_double2(-a.y, a.x);
+}
+
+// V[k] = sum_m v[m] exp(S 2 pi i m k / 8), natural order in and out.
+template <int S>
+__device__ inline void dft8(double2 (&v)[8]) {
+  constexpr double c = 0.70710678118654752440;
+  double2 e[4], o[4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {                    // the two length-4 transforms, even and odd inputs
+    const double2 a0 = v[h], a1 = v[h + 2], a2 = v[h + 4], a3 = v[h + 6];
+    const double2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = mul_j(csub(a1, a3), S);
+    double2* r = h ? o : e;
+    r[0] = cadd(t0, t2);
+    r[2] = csub(t0, t2);
+    r[1] = cadd(t1, t3);
+    r[3] = csub(t1, t3);
+  }
+  // W^k o[k], W = exp(S i pi / 4)
+  const double2 w1 = make_double2(c, S * c), w3 = make_double2(-c, S * c);
+  const double2 p0 = o[0], p1 = cmul(w1, o[1]), p2 = mul_j(o[2], S), p3 = cmul(w3, o[3]);
+  v[0] = cadd(e[0], p0);
+  v[4] = csub(e[0], p0);
+  v[1] = cadd(e[1], p1);
+  v[5] = csub(e[1], p1);
+  v[2] = cadd(e[2], p2);
+  v[6] = csub(e[2], p2);
+  v[3] = cadd(e[3], p3);
+  v[7] = csub(e[3], p3);
+}
+
+// Order the wave's LDS accesses: writes of every lane before any later read.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Forward transform: lane t holds z[t + 64 m] in v[m]; on return lane
+// (k1 + 8 k2) holds Z[k2 + 8 k1 + 64 k0] in v[k0].  X is the wave's LDS slice,
+// tw[r] = exp(-2 pi i r / 512).
+__device__ inline void fft512_fwd(double2 (&v)[8], double2* X, const double2* tw, uint32_t lane) {
+  dft8<-1>(v);
+#pragma unroll
+  for (int k2 = 1; k2 < 8; ++k2) v[k2] = cmul(v[k2], tw[(lane * k2) & 511u]);
+#pragma unroll
+  for (int k2 = 0; k2 < 8; ++k2) X[k2 * L512_ROW + lane] = v[k2];
+  wave_lds_sync();
+  const uint32_t t1 = lane & 7u, k2 = lane >> 3;
+#pragma unroll
+  for (int t2 = 0; t2 < 8; ++t2) v[t2] = X[k2 * L512_ROW + t1 + 8 * t2];
+  wave_lds_sync();
+  dft8<-1>(v);
+#pragma unroll
+  for (int k1 = 1; k1 < 8; ++k1) v[k1] = cmul(v[k1], tw[(8u * t1 * k1) & 511u]);
+#pragma unroll
+  for (int k1 = 0; k1 < 8; ++k1) X[k2 * L512_ROW + 8 * k1 + t1] = v[k1];
+  wave_lds_sync();
+  const uint32_t k1 = lane & 7u;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) v[u] = X[k2 * L512_ROW + 8 * k1 + u];
+  wave_lds_sync();
+  dft8<-1>(v);
+}
+
+// Inverse (unnormalised): lane (k1 + 8 k2) holds Z[k2 + 8 k1 + 64 k0] in v[k0];
+// on return lane t holds z[t + 64 m] in v[m].
+__device__ inline void fft512_inv(double2 (&v)[8], double2* X, const double2* tw, uint32_t lane) {
+  dft8<1>(v);                                       // over k0: index t1
+  const uint32_t k1 = lane & 7u, k2 = lane >> 3;
+#pragma unroll
+  for (int t1 = 0; t1 < 8; ++t1) X[k2 * L512_ROW + 8 * k1 + t1] = v[t1];
+  wave_lds_sync();
+  const uint32_t t1 = lane & 7u;
+#pragma unroll
+  for (int kk = 0; kk < 8; ++kk) v[kk] = cmul(X[k2 * L512_ROW + 8 * kk + t1], conj2(tw[(8u * t1 * kk) & 511u]));
+  wave_lds_sync();
+  dft8<1>(v);                                       // over k1: index t2
+#pragma unroll
+  for (int t2 = 0; t2 < 8; ++t2) X[k2 * L512_ROW + t1 + 8 * t2] = v[t2];
+  wave_lds_sync();
+#pragma unroll
+  for (int q = 0; q < 8; ++q) v[q] = cmul(X[q * L512_ROW + lane], conj2(tw[(lane * q) & 511u]));
+  wave_lds_sync();
+  dft8<1>(v);                                       // over k2: index m
+}
+
+// Spectral derivative of 512-point lines (any axis), as k_deriv_axis: two
+// adjacent lines per complex transform, the result times `sign` stored into
+// or added to the accumulator.  A block of eight wavefronts takes a group of
+// eight line pairs (sixteen consecutive lines), one wavefront per pair, groups
+// in XCD-contiguous order.  Along x a lane reads its eight points straight
+// from memory (each load covers 64 consecutive points).  Along y and z the
+// sixteen lines are neighbours in x, so the block reads and writes them
+// through LDS in rows of sixteen consecutive x (whole 128-byte lines),
+// instead of 64 separate rows per load.
+//
+// The last pass (z, into div u) can also reduce the eps sums of Eq. (7): with
+// da.eps set it reads mu, omega_x, omega_y and omega_z at each point, adds
+// mu |omega|^2 and mu (div u)^2 to the block's partial, and does not store
+// div u, which nothing reads afterwards.
+constexpr int W512 = 8;                            // wavefronts per block of the 512-point kernels
+template <bool EPS>
+__global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict__ uc, double* __restrict__ acc,
+                                                        const Geom g, const DerivAxis da,
+                                                        const double* __restrict__ fields,
+                                                        DiagPartial* __restrict__ partials) {
+  __shared__ double2 tw[512];
+  __shared__ double2 xch[W512 * L512_WAVE];
+  double* S = (double*)xch;                        // y, z: staging rows, S[line * 513 + j]
+  constexpr uint32_t SROW = 513;
+  constexpr uint32_t GL = 2 * W512;                // lines per group
+  for (uint32_t r = threadIdx.x; r < 512; r += blockDim.x) {
+    double sn, cs;
+    sincospi(-(double)r / 256.0, &sn, &cs);
+    tw[r] = make_double2(cs, sn);
+  }
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  double2* X = xch + wave * L512_WAVE;
+  const GroupRange gr = xcd_groups((da.nlines + GL - 1) / GL);
+  const double kf = da.kscale / 512.0;
+  double eps_s = 0.0, eps_d = 0.0;
+  const uint32_t kb = (lane >> 3) + 8u * (lane & 7u);   // k = kb + 64 k0 after the forward transform
+  for (uint32_t grp = gr.begin; grp < gr.end; grp += gr.step) {
+    const uint32_t lfirst = GL * grp;                  // first line of the group
+    const uint32_t nl = min(GL, da.nlines - lfirst);   // lines in the group
+    const uint32_t l0 = lfirst + 2 * wave;             // this wave's pair
+    const bool live = 2 * wave < nl, two = 2 * wave + 1 < nl;
+    double2 v[8];
+    __syncthreads();
+    if (da.axis == 0) {
+      if (live) {
+        const uint32_t b0 = line_base(l0, 0, g), b1 = two ? line_base(l0 + 1, 0, g) : b0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t j = lane + 64u * m;
+          v[m] = make_double2(uc[b0 + j], two ? uc[b1 + j] : 0.0);
+        }
+      }
+    } else {
+      for (uint32_t e = threadIdx.x; e < GL * 512; e += 64 * W512) {
+        const uint32_t ln = e % GL, j = e / GL;
+        S[ln * SROW + j] = ln < nl ? uc[line_base(lfirst + ln, da.axis, g) + j * da.stride] : 0.0;
+      }
+      __syncthreads();
+      if (live) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t j = lane + 64u * m;
+          v[m] = make_double2(S[(2 * wave) * SROW + j], two ? S[(2 * wave + 1) * SROW + j] : 0.0);
+        }
+      }
+      __syncthreads();                                 // the exchanges below reuse S
+    }
+    if (live) {
+      fft512_fwd(v, X, tw, lane);
+      // times i kappa / 512, the Nyquist mode to zero
+#pragma unroll
+      for (int k0 = 0; k0 < 8; ++k0) {
+        const uint32_t k = kb + 64u * k0;
+        const double ks = k < 256u ? (double)k : (k == 256u ? 0.0 : (double)k - 512.0);
+        const double f = ks * kf;
+        v[k0] = make_double2(-f * v[k0].y, f * v[k0].x);
+      }
+      fft512_inv(v, X, tw, lane);
+    }
+    if (da.axis == 0) {
+      if (live) {
+        const uint32_t b0 = line_base(l0, 0, g), b1 = two ? line_base(l0 + 1, 0, g) : b0;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t j = lane + 64u * m;
+          acc[b0 + j] = da.init ? da.sign * v[m].x : acc[b0 + j] + da.sign * v[m].x;
+          if (two) acc[b1 + j] = da.init ? da.sign * v[m].y : acc[b1 + j] + da.sign * v[m].y;
+        }
+      }
+    } else {
+      __syncthreads();                                 // every wave is done with its exchanges
+      if (live) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t j = lane + 64u * m;
+          S[(2 * wave) * SROW + j] = v[m].x;
+          if (two) S[(2 * wave + 1) * SROW + j] = v[m].y;
+        }
+      }
+      __syncthreads();
+      const uint64_t N = g.ncells;
+      for (uint32_t e = threadIdx.x; e < GL * 512; e += 64 * W512) {
+        const uint32_t ln = e % GL, j = e / GL;
+        if (ln >= nl) continue;
+        const uint32_t a = line_base(lfirst + ln, da.axis, g) + j * da.stride;
+        const double d = (da.init ? 0.0 : acc[a]) + da.sign * S[ln * SROW + j];
+        if constexpr (EPS) {
+          const double m = fields[3 * N + a], x = fields[5 * N + a], y = fields[6 * N + a], z = fields[7 * N + a];
+          eps_s += m * (x * x + y * y + z * z);
+          eps_d += m * d * d;
+        } else {
+          acc[a] = d;
+        }
+      }
+    }
+  }
+  if constexpr (EPS) {
+    // block sums in a fixed order: wave shuffles, then the waves in index order
+    __shared__ double red[2][W512];
+    eps_s = wave_sum(eps_s);
+    eps_d = wave_sum(eps_d);
+    __syncthreads();
+    if (lane == 0) {
+      red[0][wave] = eps_s;
+      red[1][wave] = eps_d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double ts = red[0][0], td = red[1][0];
+      for (int w = 1; w < W512; ++w) {
+        ts += red[0][w];
+        td += red[1][w];
+      }
+      if (da.eps == 2) {
+        DiagPartial p;
+        part_zero(p);
+        p.eps_s = ts;
+        p.eps_d = td;
+        partials[blockIdx.x] = p;
+      } else {
+        partials[blockIdx.x].eps_s = ts;
+        partials[blockIdx.x].eps_d = td;
+      }
+    }
+  }
+}
+
 // eps sums: sum of mu |omega|^2 and mu (div u)^2 over the cells, per block,
 // into the eps fields of the block's partial (full: a whole partial, the
 // other fields neutral).
@@ -413,6 +668,108 @@ __global__ void __launch_bounds__(DB) k_spectrum_axis(const double* __restrict__
   }
 }
 
+// Forward transform of 512-point lines for the shell spectrum (as
+// k_spectrum_axis, same modes): one wavefront per complex line, eight
+// consecutive lines per block, the register transform of the derivative
+// passes, results in natural order.  Along y and z the eight lines are
+// neighbours in x and go through LDS in rows of eight (128-byte runs).
+__global__ void __launch_bounds__(64 * W512) k_spectrum512(const double* __restrict__ real_in,
+                                                           double2* __restrict__ data, double* __restrict__ energy,
+                                                           const Geom g, const SpecAxis sa) {
+  __shared__ double2 tw[512];
+  __shared__ double2 xch[W512 * L512_WAVE];
+  double2* S = xch;                                // y, z: staging rows, S[line * 513 + k]
+  constexpr uint32_t SROW = 513;
+  for (uint32_t r = threadIdx.x; r < 512; r += blockDim.x) {
+    double sn, cs;
+    sincospi(-(double)r / 256.0, &sn, &cs);
+    tw[r] = make_double2(cs, sn);
+  }
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  double2* X = xch + wave * L512_WAVE;
+  constexpr uint32_t GL = W512;                    // lines per group
+  const GroupRange gr = xcd_groups((sa.nlines + GL - 1) / GL);
+  const uint32_t kb = (lane >> 3) + 8u * (lane & 7u);
+  for (uint32_t grp = gr.begin; grp < gr.end; grp += gr.step) {
+    const uint32_t lfirst = GL * grp, nl = min(GL, sa.nlines - lfirst);
+    const uint32_t line = lfirst + wave;
+    const bool live = wave < nl;
+    double2 v[8];
+    __syncthreads();
+    if (sa.axis == 0) {
+      if (live) {
+        const uint32_t b = line_base(line, 0, g);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const uint32_t addr = b + lane + 64u * m;
+          v[m] = sa.mode == 0 ? make_double2(real_in[addr], 0.0) : data[addr];
+        }
+      }
+    } else {
+      constexpr int PER = GL * 512 / (64 * W512);
+      double2 ld[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t e = threadIdx.x + q * (64 * W512), ln = e % GL, j = e / GL;
+        const uint32_t addr = ln < nl ? line_base(lfirst + ln, sa.axis, g) + j * sa.stride : 0u;
+        ld[q] = sa.mode == 0 ? make_double2(real_in[addr], 0.0) : data[addr];
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t e = threadIdx.x + q * (64 * W512), ln = e % GL, j = e / GL;
+        S[ln * SROW + j] = ld[q];
+      }
+      __syncthreads();
+      if (live) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) v[m] = S[wave * SROW + lane + 64u * m];
+      }
+      __syncthreads();                                 // the exchanges below reuse S
+    }
+    if (live) fft512_fwd(v, X, tw, lane);
+    if (sa.axis == 0) {
+      if (live) {
+        const uint32_t b = line_base(line, 0, g);
+#pragma unroll
+        for (int k0 = 0; k0 < 8; ++k0) {
+          const uint32_t addr = b + kb + 64u * k0;
+          if (sa.mode == 2) {
+            const double e = (v[k0].x * v[k0].x + v[k0].y * v[k0].y) * sa.escale;
+            energy[addr] = sa.accumulate ? energy[addr] + e : e;
+          } else {
+            data[addr] = v[k0];
+          }
+        }
+      }
+    } else {
+      __syncthreads();
+      if (live) {
+#pragma unroll
+        for (int k0 = 0; k0 < 8; ++k0) S[wave * SROW + kb + 64u * k0] = v[k0];
+      }
+      __syncthreads();
+      constexpr int PER = GL * 512 / (64 * W512);
+      double ev[PER];
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t e = threadIdx.x + q * (64 * W512), ln = e % GL, k = e / GL;
+        ev[q] = (sa.mode == 2 && sa.accumulate && ln < nl) ? energy[line_base(lfirst + ln, sa.axis, g) + k * sa.stride]
+                                                            : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const uint32_t e = threadIdx.x + q * (64 * W512), ln = e % GL, k = e / GL;
+        if (ln < nl) {
+          const uint32_t addr = line_base(lfirst + ln, sa.axis, g) + k * sa.stride;
+          const double2 Xv = S[ln * SROW + k];
+          if (sa.mode == 2) energy[addr] = ev[q] + (Xv.x * Xv.x + Xv.y * Xv.y) * sa.escale;
+          else data[addr] = Xv;
+        }
+      }
+    }
+  }
+}
+
 // Integer wavenumber of DFT index j on an axis of n points.
 __device__ inline int64_t wavenumber(uint32_t j, uint32_t n) { return j < (n + 1) / 2 ? (int64_t)j : (int64_t)j - n; }
 
@@ -473,6 +830,17 @@ __global__ void k_shell_final(const double* __restrict__ partial, uint32_t nplan
   E[k] = acc;
 }
 
+// Sums of consecutive chunks of partials, one block per chunk, in a fixed order.
+__global__ void k_diag_chunks(const DiagPartial* __restrict__ partials, int nparts, int chunk,
+                              DiagPartial* __restrict__ out) {
+  DiagPartial acc;
+  part_zero(acc);
+  const int lo = blockIdx.x * chunk, hi = min(nparts, lo + chunk);
+  for (int i = lo + (int)threadIdx.x; i < hi; i += DB) part_add(acc, partials[i]);
+  DiagPartial tot = block_reduce(acc);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
+}
+
 __global__ void k_diag_final(const DiagPartial* __restrict__ partials, int nparts, DiagPartial* __restrict__ out) {
   DiagPartial acc;
   part_zero(acc);
@@ -515,6 +883,8 @@ hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial
       {0, 0, 0, 1.0, 1}, {0, 1, 3, 1.0, 1}, {0, 2, 2, -1.0, 1},   // div; omega_z += d_x v; omega_y -= d_x w
       {1, 0, 3, -1.0, 0}, {1, 1, 0, 1.0, 0}, {1, 2, 1, 1.0, 1},   // omega_z -= d_y u; div; omega_x += d_y w
       {2, 0, 2, 1.0, 0}, {2, 1, 1, -1.0, 0}, {2, 2, 0, 1.0, 0}};  // omega_y += d_z u; omega_x -= d_z v; div
+  // the eps sums ride on the last pass when it takes the 512-point kernel
+  const bool fuse_eps = g.nz == 512 && CNSF_DERIV_512;
   for (const Pass& ps : passes) {
     DerivAxis da{};
     da.n = dims[ps.a];
@@ -536,11 +906,20 @@ hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial
     da.sign = ps.sign;
     da.kscale = 2.0 * M_PI / ((double)da.n * dx);
     const size_t lds = (size_t)rows * da.pairs_per_block * lds_line(da.n) * sizeof(double2) + extra;
-    hipLaunchKernelGGL(k_deriv_axis, dim3(DIAG_BLOCKS), dim3(DB), lds, s, fields + ps.c * N,
-                       fields + (4 + ps.target) * N, g, da);
+    if (fuse_eps && &ps == &passes[8]) da.eps = full ? 2 : 1;
+    if (da.n == 512 && CNSF_DERIV_512 && da.eps)
+      hipLaunchKernelGGL(k_deriv512<true>, dim3(DIAG_BLOCKS), dim3(64 * W512), 0, s, fields + ps.c * N,
+                         fields + (4 + ps.target) * N, g, da, (const double*)fields, partials);
+    else if (da.n == 512 && CNSF_DERIV_512)
+      hipLaunchKernelGGL(k_deriv512<false>, dim3(DIAG_BLOCKS), dim3(64 * W512), 0, s, fields + ps.c * N,
+                         fields + (4 + ps.target) * N, g, da, (const double*)fields, partials);
+    else
+      hipLaunchKernelGGL(k_deriv_axis, dim3(DIAG_BLOCKS), dim3(DB), lds, s, fields + ps.c * N,
+                         fields + (4 + ps.target) * N, g, da);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  if (fuse_eps) return hipSuccess;
   hipLaunchKernelGGL(k_eps_sums, dim3(DIAG_BLOCKS), dim3(DB), 0, s, fields, g, partials, full ? 1 : 0);
   return hipGetLastError();
 }
@@ -579,7 +958,12 @@ hipError_t launch_spectrum(const Geom& g, double* fields, double* partial, doubl
       sa.accumulate = c > 0;
       sa.escale = 0.5 / (n3 * n3);
       const size_t lds_a = (size_t)rows * sa.lines_per_block * lds_line(n) * sizeof(double2) + extra;
-      hipLaunchKernelGGL(k_spectrum_axis, dim3(DIAG_BLOCKS), dim3(DB), lds_a, s, fields + c * N, data, energy, g, sa);
+      if (n == 512 && CNSF_DERIV_512)
+        hipLaunchKernelGGL(k_spectrum512, dim3(DIAG_BLOCKS), dim3(64 * W512), 0, s, fields + c * N, data, energy, g,
+                           sa);
+      else
+        hipLaunchKernelGGL(k_spectrum_axis, dim3(DIAG_BLOCKS), dim3(DB), lds_a, s, fields + c * N, data, energy, g,
+                           sa);
       hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
@@ -594,6 +978,17 @@ hipError_t launch_spectrum(const Geom& g, double* fields, double* partial, doubl
 hipError_t launch_diag_final(DiagPartial* partials, int nparts, DiagPartial* out, hipStream_t s) {
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DB), 0, s, partials, nparts, out);
   return hipGetLastError();
+}
+
+hipError_t launch_diag_final2(DiagPartial* partials, int nparts, DiagPartial* tmp, int ntmp, DiagPartial* out,
+                              hipStream_t s) {
+  if (!tmp || ntmp < 1 || nparts <= 4 * DB) return launch_diag_final(partials, nparts, out, s);
+  const int nb = std::min(ntmp, (nparts + 4 * DB - 1) / (4 * DB));
+  const int chunk = (nparts + nb - 1) / nb;
+  hipLaunchKernelGGL(k_diag_chunks, dim3(nb), dim3(DB), 0, s, partials, nparts, chunk, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_diag_final(tmp, nb, out, s);
 }
 
 }  // namespace cnsf

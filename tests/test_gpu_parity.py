@@ -267,6 +267,25 @@ def test_diagnostics_non_power_of_two_axes():
         assert abs(d[k] - o[k]) <= 1e-9 * max(abs(o[k]), 1e-12), (k, d[k], o[k])
 
 
+@pytest.mark.parametrize("dims", [(512, 4, 6), (6, 512, 4), (4, 6, 512)])
+def test_diagnostics_512_point_axes(dims):
+    """Lines of 512 points take the register transform of the derivative passes
+    along any axis; a white-noise state puts energy in every mode, so each
+    twiddle and index of that transform shows in eps_s and eps_d (against the
+    oracle's numpy.fft derivatives on the same state, 1e-9)."""
+    cnsf = _cnsf()
+    case = W.random_case(*dims, seed=12, sensor=True, amp=0.5)
+    log(f"case {case.name} diagnostics")
+    L = cnsf.Lattice(case.params)
+    L.set_state(case.Q0)
+    L.step(2)
+    d = L.diagnostics(spectral=True)
+    o = odiag.diagnostics(L.moments(), case.params)
+    log(f"  gpu eps_s {d['eps_s']:.12e} eps_d {d['eps_d']:.12e}; oracle {o['eps_s']:.12e} {o['eps_d']:.12e}")
+    for k in ("E_k", "eps_s", "eps_d"):
+        assert abs(d[k] - o[k]) <= 1e-9 * max(abs(o[k]), 1e-12), (k, d[k], o[k])
+
+
 _STEP_DIAG_CASES = {
     "random_fp32": (lambda: W.random_case(13, 11, 9, seed=5, sensor=True, amp=0.5), W.STORAGE_FP32, None, 4, 6),
     "random_fp16": (lambda: W.random_case(13, 11, 9, seed=5, sensor=True, amp=0.5), W.STORAGE_FP16, None, 4, 6),
