@@ -4,8 +4,13 @@ usage:
   python -m paper_2608_13437_amd.profile_summary stats  <kernel_stats.csv> <out.txt> "<command>" [bench.log]
   python -m paper_2608_13437_amd.profile_summary traffic <fetch.csv> <write.csv> <copy_fetch.csv>
          <copy_write.csv> <copy_bytes> <storage> <out.json> "<commands>"
+  python -m paper_2608_13437_amd.profile_summary requests <dram.csv> <copy_dram.csv> <copy_bytes>
+         <storage> <out.json> "<command>"
 The traffic summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the
 update by the factor the same counter needs on a plain copy of known size.
+The requests summary does the same with the DRAM read and write request
+counts (TCC_EA0_RDREQ_DRAM_sum, TCC_EA0_WRREQ_DRAM_sum), a cross-check of
+the first from another counter.
 """
 import csv
 import hashlib
@@ -96,8 +101,33 @@ def traffic(fetch, write, cfetch, cwrite, copy_bytes, storage, out, command):
     json.dump(rec, open(out, "w"), indent=1)
 
 
+def _by_counter(path, pattern):
+    out = {}
+    for r in csv.DictReader(open(path)):
+        if pattern.search(r["Kernel_Name"]):
+            out.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def requests(dram, cdram, copy_bytes, storage, out, command):
+    u, c = _by_counter(dram, UPDATE), _by_counter(cdram, COPY)
+    copy_bytes = int(copy_bytes)
+    rd, wr = "TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_WRREQ_DRAM_sum"
+    # a copy reads and writes copy_bytes: bytes per request of each kind
+    rsz = copy_bytes / (sum(c[rd]) / len(c[rd]))
+    wsz = copy_bytes / (sum(c[wr]) / len(c[wr]))
+    per = [a * rsz + b * wsz for a, b in zip(u[rd], u[wr])]
+    rec = json.load(open(out)) if os.path.exists(out) else {}
+    rec.setdefault(storage, {})["dram_requests"] = dict(
+        bytes_per_read=round(rsz, 2), bytes_per_write=round(wsz, 2),
+        bytes_per_launch=round(sum(per) / len(per)), launches=len(per), command=command)
+    json.dump(rec, open(out, "w"), indent=1)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:6])
+    elif sys.argv[1] == "requests":
+        requests(*sys.argv[2:8])
     else:
         traffic(*sys.argv[2:10])
