@@ -7,6 +7,9 @@ EVERY steps.
 
 usage: python tests/golden/make_tgv_history.py [N] [T_END] [EVERY] [F_MU] [M0] [RE] [LAW]
 
+The file name carries N, F_MU (if given), M0 and RE (if given), LAW (if not
+the power law) and T_END (if not 20).
+
 The defaults are the supersonic case; the subsonic verification case of
 Section 3.2 is M0 0.5, Re 500 with F_MU 0.  LAW is the viscosity law:
 "power" (mu ~ T^0.76, the default), "sutherland" or "const" (mu = 1/Re
@@ -47,6 +50,8 @@ def main():
         tag += f"_M{M0:g}_Re{Re:g}"
     if law != "power":
         tag += f"_{law}"
+    if t_end != 20.0:
+        tag += f"_t{t_end:g}"
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"tgv{n}{tag}_history.json")
     hist = dict(step=[], t=[], E_k=[], eps_s=[], eps_d=[], mass=[], energy=[])
     f = lbm.init_populations(case.Q0, prm)
