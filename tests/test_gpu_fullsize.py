@@ -72,6 +72,12 @@ def test_tgv512_probes_match_oracle(storage, bound):
                     {k: np.concatenate([r[k].ravel() for r in ref]) for k in ref[0]})
     log(f"  pooled over {len(got)} probes: {pooled}")
     assert all(v < bound for v in pooled.values()), pooled
+    # and no single cube may hide a local error: each cube's RMS error over
+    # the RMS of the field over all cubes
+    scale = {k: np.sqrt(np.mean(np.concatenate([r[k].ravel() for r in ref]) ** 2)) for k in ref[0]}
+    for (c, g, r) in zip(gold["centres"], got, ref):
+        e = {k: float(np.sqrt(np.mean((g[k] - r[k]) ** 2)) / scale[k]) for k in r}
+        assert all(v < bound for v in e.values()), (tuple(int(x) for x in c), e)
     d = L.diagnostics(spectral=False)
     assert d["nonfinite"] == 0
     L.close()
