@@ -697,8 +697,7 @@ int cnsf_spectrum(cnsf_lattice* L, double* E, int32_t nshells, int32_t where) {
   }
   double* dE = where == CNSF_DEVICE ? E : L->spec + npart;
   const uint32_t nout = where == CNSF_DEVICE ? (uint32_t)nshells : (uint32_t)need;
-  e = launch_diag_sums(L->p.storage, L->pop, L->g, L->ph, L->phd, L->cd, L->parity, L->partials, L->fields,
-                       L->stream);
+  e = launch_velocity(L->p.storage, L->pop, L->g, L->cd, L->parity, L->fields, L->stream);
   if (e == hipSuccess) e = launch_spectrum(L->g, L->fields, L->spec, dE, nout, L->stream);
   if (e == hipSuccess && where == CNSF_HOST) {
     e = hipMemcpyAsync(E, dE, (size_t)need * sizeof(double), hipMemcpyDeviceToHost, L->stream);

@@ -79,6 +79,39 @@ __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* _
   if (threadIdx.x == 0) partials[blockIdx.x] = tot;
 }
 
+// The velocity alone, for the shell spectrum of a periodic lattice: only the
+// 28 populations of rho and rho u are read (136 bytes per FP32 cell against
+// the 392 + 32 of the full readout), and u = rho u / rho is formed exactly as
+// the full readout forms it (FP64 sums of the stored values in slot order),
+// so the fields are bitwise the same.
+template <int ST>
+__global__ void __launch_bounds__(DB) k_velocity(const typename Store<ST>::T* __restrict__ pop, const Geom g,
+                                                 const Codec cd, int parity, double* __restrict__ fields) {
+  const uint32_t stride = gridDim.x * DB;
+  for (uint32_t c = blockIdx.x * DB + threadIdx.x; c < g.ncells; c += stride) {
+    const Nbr n = neighbours(c, g);
+    uint32_t off[NV];
+    stream_offsets<ST, 0>(g, n, parity, off);
+    double Q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const __amdgpu_buffer_rsrc_t rs = component_rsrc<ST>(pop, g, k);
+      double sum = 0.0;
+#pragma unroll
+      for (int i = 0; i < NV; ++i) {
+        float v = buf_load<ST>(rs, off[i]);
+        if (ST != 0) v *= cd.scale[k];
+        sum += (double)v;
+      }
+      Q[k] = q_ref<double>(cd, k) + sum;
+    }
+    const double inv_rho = 1.0 / Q[0];
+    fields[c] = Q[1] * inv_rho;
+    fields[g.ncells + c] = Q[2] * inv_rho;
+    fields[2 * (uint64_t)g.ncells + c] = Q[3] * inv_rho;
+  }
+}
+
 // ------------------------------------------------------------------ spectral
 // One derivative pass: d_a u_c for every line along axis a.
 struct DerivAxis {
@@ -436,6 +469,9 @@ __device__ inline void fft512_inv(double2 (&v)[8], double2* X, const double2* tw
 // mu |omega|^2 and mu (div u)^2 to the block's partial, and does not store
 // div u, which nothing reads afterwards.
 constexpr int W512 = 8;                            // wavefronts per block of the 512-point kernels
+#ifndef CNSF_EPS_BATCH
+#define CNSF_EPS_BATCH 2                           // points per thread whose eps inputs load together
+#endif
 template <bool EPS>
 __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict__ uc, double* __restrict__ acc,
                                                         const Geom g, const DerivAxis da,
@@ -457,11 +493,20 @@ __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict
   const double kf = da.kscale / 512.0;
   double eps_s = 0.0, eps_d = 0.0;
   const uint32_t kb = (lane >> 3) + 8u * (lane & 7u);   // k = kb + 64 k0 after the forward transform
+  // y and z staging: thread t serves line sn = t mod GL of its group at the
+  // points j0 + JSTEP q, q < PER
+  constexpr uint32_t JSTEP = 64 * W512 / GL, PER = 512 / JSTEP;
+  static_assert((64 * W512) % GL == 0 && 512 % JSTEP == 0, "staging layout");
+  const uint32_t sn = threadIdx.x % GL, j0 = threadIdx.x / GL;
+  const uint64_t qstep = (uint64_t)JSTEP * da.stride;   // elements between a thread's points
+  double ld[PER];
   for (uint32_t grp = gr.begin; grp < gr.end; grp += gr.step) {
     const uint32_t lfirst = GL * grp;                  // first line of the group
     const uint32_t nl = min(GL, da.nlines - lfirst);   // lines in the group
     const uint32_t l0 = lfirst + 2 * wave;             // this wave's pair
     const bool live = 2 * wave < nl, two = 2 * wave + 1 < nl;
+    const bool sl = sn < nl;                           // this thread's staging line exists
+    const uint32_t toff = sl ? line_base(lfirst + sn, da.axis, g) + j0 * da.stride : 0u;
     double2 v[8];
     __syncthreads();
     if (da.axis == 0) {
@@ -474,10 +519,13 @@ __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict
         }
       }
     } else {
-      for (uint32_t e = threadIdx.x; e < GL * 512; e += 64 * W512) {
-        const uint32_t ln = e % GL, j = e / GL;
-        S[ln * SROW + j] = ln < nl ? uc[line_base(lfirst + ln, da.axis, g) + j * da.stride] : 0.0;
-      }
+      // Thread t always serves line t mod GL at points j0 + JSTEP q: one
+      // per-thread offset and a block-uniform step, so all PER loads are in
+      // flight before the first LDS write.
+#pragma unroll
+      for (int q = 0; q < PER; ++q) ld[q] = sl ? (uc + q * qstep)[toff] : 0.0;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) S[sn * SROW + j0 + JSTEP * q] = ld[q];
       __syncthreads();
       if (live) {
 #pragma unroll
@@ -521,18 +569,34 @@ __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict
         }
       }
       __syncthreads();
-      const uint64_t N = g.ncells;
-      for (uint32_t e = threadIdx.x; e < GL * 512; e += 64 * W512) {
-        const uint32_t ln = e % GL, j = e / GL;
-        if (ln >= nl) continue;
-        const uint32_t a = line_base(lfirst + ln, da.axis, g) + j * da.stride;
-        const double d = (da.init ? 0.0 : acc[a]) + da.sign * S[ln * SROW + j];
-        if constexpr (EPS) {
-          const double m = fields[3 * N + a], x = fields[5 * N + a], y = fields[6 * N + a], z = fields[7 * N + a];
-          eps_s += m * (x * x + y * y + z * z);
-          eps_d += m * d * d;
-        } else {
-          acc[a] = d;
+      if constexpr (EPS) {
+        const uint64_t N = g.ncells;
+        constexpr int EB = CNSF_EPS_BATCH;
+#pragma unroll 1
+        for (int q0 = 0; q0 < (int)PER; q0 += EB) {    // 5 EB loads in flight per batch
+          double av[EB], mv[EB], xv[EB], yv[EB], zv[EB];
+#pragma unroll
+          for (int q = 0; q < EB; ++q) {
+            const uint64_t o = (uint64_t)(q0 + q) * qstep;
+            av[q] = (sl && !da.init) ? (acc + o)[toff] : 0.0;
+            mv[q] = sl ? (fields + 3 * N + o)[toff] : 0.0;
+            xv[q] = sl ? (fields + 5 * N + o)[toff] : 0.0;
+            yv[q] = sl ? (fields + 6 * N + o)[toff] : 0.0;
+            zv[q] = sl ? (fields + 7 * N + o)[toff] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < EB; ++q) {
+            const double d = av[q] + da.sign * S[sn * SROW + j0 + JSTEP * (q0 + q)];
+            eps_s += mv[q] * (xv[q] * xv[q] + yv[q] * yv[q] + zv[q] * zv[q]);
+            eps_d += mv[q] * d * d;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) ld[q] = (sl && !da.init) ? (acc + q * qstep)[toff] : 0.0;
+        if (sl) {
+#pragma unroll
+          for (int q = 0; q < PER; ++q) (acc + q * qstep)[toff] = ld[q] + da.sign * S[sn * SROW + j0 + JSTEP * q];
         }
       }
     }
@@ -690,10 +754,18 @@ __global__ void __launch_bounds__(64 * W512) k_spectrum512(const double* __restr
   constexpr uint32_t GL = W512;                    // lines per group
   const GroupRange gr = xcd_groups((sa.nlines + GL - 1) / GL);
   const uint32_t kb = (lane >> 3) + 8u * (lane & 7u);
+  // y and z staging: thread t serves line sn = t mod GL of its group at the
+  // points j0 + JSTEP q, q < PER (one per-thread offset, a block-uniform step)
+  constexpr uint32_t JSTEP = 64 * W512 / GL, PER = 512 / JSTEP;
+  static_assert((64 * W512) % GL == 0 && 512 % JSTEP == 0, "staging layout");
+  const uint32_t sn = threadIdx.x % GL, j0 = threadIdx.x / GL;
+  const uint64_t qstep = (uint64_t)JSTEP * sa.stride;
   for (uint32_t grp = gr.begin; grp < gr.end; grp += gr.step) {
     const uint32_t lfirst = GL * grp, nl = min(GL, sa.nlines - lfirst);
     const uint32_t line = lfirst + wave;
     const bool live = wave < nl;
+    const bool sl = sn < nl;
+    const uint32_t toff = sl ? line_base(lfirst + sn, sa.axis, g) + j0 * sa.stride : 0u;
     double2 v[8];
     __syncthreads();
     if (sa.axis == 0) {
@@ -706,19 +778,17 @@ __global__ void __launch_bounds__(64 * W512) k_spectrum512(const double* __restr
         }
       }
     } else {
-      constexpr int PER = GL * 512 / (64 * W512);
+      // all of the thread's loads in flight before the LDS writes
       double2 ld[PER];
+      if (sa.mode == 0) {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const uint32_t e = threadIdx.x + q * (64 * W512), ln = e % GL, j = e / GL;
-        const uint32_t addr = ln < nl ? line_base(lfirst + ln, sa.axis, g) + j * sa.stride : 0u;
-        ld[q] = sa.mode == 0 ? make_double2(real_in[addr], 0.0) : data[addr];
+        for (int q = 0; q < (int)PER; ++q) ld[q] = make_double2(sl ? (real_in + q * qstep)[toff] : 0.0, 0.0);
+      } else {
+#pragma unroll
+        for (int q = 0; q < (int)PER; ++q) ld[q] = sl ? (data + q * qstep)[toff] : make_double2(0.0, 0.0);
       }
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const uint32_t e = threadIdx.x + q * (64 * W512), ln = e % GL, j = e / GL;
-        S[ln * SROW + j] = ld[q];
-      }
+      for (int q = 0; q < (int)PER; ++q) S[sn * SROW + j0 + JSTEP * q] = ld[q];
       __syncthreads();
       if (live) {
 #pragma unroll
@@ -748,23 +818,20 @@ __global__ void __launch_bounds__(64 * W512) k_spectrum512(const double* __restr
         for (int k0 = 0; k0 < 8; ++k0) S[wave * SROW + kb + 64u * k0] = v[k0];
       }
       __syncthreads();
-      constexpr int PER = GL * 512 / (64 * W512);
-      double ev[PER];
+      if (sa.mode == 2) {
+        double ev[PER];
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const uint32_t e = threadIdx.x + q * (64 * W512), ln = e % GL, k = e / GL;
-        ev[q] = (sa.mode == 2 && sa.accumulate && ln < nl) ? energy[line_base(lfirst + ln, sa.axis, g) + k * sa.stride]
-                                                            : 0.0;
-      }
+        for (int q = 0; q < (int)PER; ++q) ev[q] = (sl && sa.accumulate) ? (energy + q * qstep)[toff] : 0.0;
+        if (sl) {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const uint32_t e = threadIdx.x + q * (64 * W512), ln = e % GL, k = e / GL;
-        if (ln < nl) {
-          const uint32_t addr = line_base(lfirst + ln, sa.axis, g) + k * sa.stride;
-          const double2 Xv = S[ln * SROW + k];
-          if (sa.mode == 2) energy[addr] = ev[q] + (Xv.x * Xv.x + Xv.y * Xv.y) * sa.escale;
-          else data[addr] = Xv;
+          for (int q = 0; q < (int)PER; ++q) {
+            const double2 Xv = S[sn * SROW + j0 + JSTEP * q];
+            (energy + q * qstep)[toff] = ev[q] + (Xv.x * Xv.x + Xv.y * Xv.y) * sa.escale;
+          }
         }
+      } else if (sl) {
+#pragma unroll
+        for (int q = 0; q < (int)PER; ++q) (data + q * qstep)[toff] = S[sn * SROW + j0 + JSTEP * q];
       }
     }
   }
@@ -850,6 +917,20 @@ __global__ void k_diag_final(const DiagPartial* __restrict__ partials, int npart
 }
 
 // ------------------------------------------------------------------ launchers
+hipError_t launch_velocity(int storage, const void* pop, const Geom& g, const Codec& cd, int parity, double* fields,
+                           hipStream_t s) {
+  if (g.bc_x != 0) return hipErrorInvalidValue;
+#define CNSF_CASE(ST)                                                                                              \
+  if (storage == ST) {                                                                                             \
+    hipLaunchKernelGGL((k_velocity<ST>), dim3(DIAG_BLOCKS), dim3(DB), 0, s, (const typename Store<ST>::T*)pop, g, \
+                       cd, parity, fields);                                                                       \
+    return hipGetLastError();                                                                                      \
+  }
+  CNSF_CASE(0) CNSF_CASE(1) CNSF_CASE(2)
+#undef CNSF_CASE
+  return hipErrorInvalidValue;
+}
+
 template <int ST, int BC>
 static hipError_t diag_sums_t(const void* pop, const Geom& g, const Phys& ph, const PhysD& phd, const Codec& cd,
                               int parity, DiagPartial* partials, double* fields, hipStream_t s) {

@@ -46,6 +46,10 @@ hipError_t launch_update_diag(int storage, void* pop, const Geom& g, const Phys&
                               hipStream_t s);
 hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const Phys& ph, const PhysD& phd,
                             const Codec& cd, int parity, DiagPartial* partials, double* fields, hipStream_t s);
+// u, v, w of a periodic lattice into fields (3 * ncells doubles), bitwise as
+// launch_diag_sums writes them, reading only the rho and rho u populations.
+hipError_t launch_velocity(int storage, const void* pop, const Geom& g, const Codec& cd, int parity, double* fields,
+                           hipStream_t s);
 // fields: u, v, w, mu (4 * ncells doubles), then div, wx, wy, wz (4 * ncells).
 // Spectral eps sums of the u, v, w, mu fields into DIAG_BLOCKS partials: only
 // their eps fields, or (full) whole partials with the other fields neutral.
