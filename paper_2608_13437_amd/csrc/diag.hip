@@ -81,9 +81,9 @@ __global__ void __launch_bounds__(DB) k_diag_sums(const typename Store<ST>::T* _
 
 // The velocity alone, for the shell spectrum of a periodic lattice: only the
 // 28 populations of rho and rho u are read (136 bytes per FP32 cell against
-// the 392 + 32 of the full readout), and u = rho u / rho is formed exactly as
-// the full readout forms it (FP64 sums of the stored values in slot order),
-// so the fields are bitwise the same.
+// the 392 + 32 of the full readout), and u = rho u / rho is formed in the
+// full readout's arithmetic (FP64 sums of the stored values in slot order,
+// then one reciprocal of rho).
 template <int ST>
 __global__ void __launch_bounds__(DB) k_velocity(const typename Store<ST>::T* __restrict__ pop, const Geom g,
                                                  const Codec cd, int parity, double* __restrict__ fields) {

@@ -46,8 +46,8 @@ hipError_t launch_update_diag(int storage, void* pop, const Geom& g, const Phys&
                               hipStream_t s);
 hipError_t launch_diag_sums(int storage, const void* pop, const Geom& g, const Phys& ph, const PhysD& phd,
                             const Codec& cd, int parity, DiagPartial* partials, double* fields, hipStream_t s);
-// u, v, w of a periodic lattice into fields (3 * ncells doubles), bitwise as
-// launch_diag_sums writes them, reading only the rho and rho u populations.
+// u, v, w of a periodic lattice into fields (3 * ncells doubles), in the
+// arithmetic of launch_diag_sums, reading only the rho and rho u populations.
 hipError_t launch_velocity(int storage, const void* pop, const Geom& g, const Codec& cd, int parity, double* fields,
                            hipStream_t s);
 // fields: u, v, w, mu (4 * ncells doubles), then div, wx, wy, wz (4 * ncells).
