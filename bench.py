@@ -88,15 +88,15 @@ def time_update(L, steps, warmup):
     return float(np.mean(per)), float(np.min(per)), wall
 
 
-SPECTRUM_BYTES_PER_CELL = {"fp32": 688, "fp16": 492, "bf16": 492}
+SPECTRUM_BYTES_PER_CELL = {"fp32": 400, "fp16": 344, "bf16": 344}
 
 
 def spectrum_timing(L, storage, reps=3):
     """Shell-averaged velocity spectrum of the current state: mean time of one call
     (velocity readout, three 3D transforms, shell sums), from HIP events on the
-    lattice's stream.  Algorithmic bytes per cell: the 98 populations read and
-    u, v, w, mu written (424 B FP32, 228 B 16-bit), 256 B for the axis passes,
-    8 B for the shell sums."""
+    lattice's stream.  Algorithmic bytes per cell: the 28 populations of rho and
+    rho u read and u, v, w written (136 B FP32, 80 B 16-bit), 256 B for the axis
+    passes, 8 B for the shell sums."""
     import torch
     E = L.spectrum(device=True)          # allocates the workspace
     torch.cuda.synchronize()

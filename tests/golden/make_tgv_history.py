@@ -5,7 +5,7 @@ Taylor-Green vortex (M0 1.25, Re 1600, Pr 0.71, mu ~ T^0.76) at N^3 from
 t_c = 0 to t_c = T_END, recording E_k, eps_s, eps_d, mass and energy every
 EVERY steps.
 
-usage: python tests/golden/make_tgv_history.py [N] [T_END] [EVERY] [F_MU] [M0] [RE] [LAW]
+usage: python tests/golden/make_tgv_history.py [N] [T_END] [EVERY] [F_MU] [M0] [RE] [LAW] [PARTIAL]
 
 The file name carries N, F_MU (if given), M0 and RE (if given), LAW (if not
 the power law) and T_END (if not 20).
@@ -42,6 +42,8 @@ def main():
     M0 = float(sys.argv[5]) if len(sys.argv) > 5 else 1.25
     Re = float(sys.argv[6]) if len(sys.argv) > 6 else 1600.0
     law = sys.argv[7] if len(sys.argv) > 7 else "power"
+    # PARTIAL > 0: also write the history so far every PARTIAL records
+    partial = int(sys.argv[8]) if len(sys.argv) > 8 else 0
     case = W.tgv(n, f_mu=f_mu, M0=M0, Re=Re, law=law)
     prm = case.params
     steps = int(np.ceil(t_end / prm["dt"] / every)) * every
@@ -56,6 +58,20 @@ def main():
     hist = dict(step=[], t=[], E_k=[], eps_s=[], eps_d=[], mass=[], energy=[])
     f = lbm.init_populations(case.Q0, prm)
     t0 = time.time()
+
+    def write(last):
+        # the history so far: a prefix of the run is itself a valid golden of
+        # `last` steps, so a long run can be stopped and still leave one
+        rec = dict(source="oracle.lbm FP64, oracle.diagnostics (Eq. (7), spectral derivatives)",
+                   case=dict(n=n, M0=M0, Re=Re, Pr=0.71,
+                             law={"power": "power 0.76", "sutherland": "Sutherland 0.4042", "const": "constant"}[law],
+                             f_mu=prm["f_mu"], dt=prm["dt"], C_sigma=prm["C_sigma"], J_min=prm["J_min"],
+                             omega_min=prm["omega_min"]),
+                   every=every, steps=last, wall_seconds=round(time.time() - t0, 1), history=hist)
+        with open(out + ".tmp", "w") as fh:
+            json.dump(rec, fh)
+        os.replace(out + ".tmp", out)
+
     for s in range(steps + 1):
         if s % every == 0:
             d = diagnostics.diagnostics(lbm.moments(f), prm)
@@ -68,14 +84,11 @@ def main():
             if s % (every * 20) == 0:
                 print(f"step {s}/{steps} t_c {s * prm['dt']:.2f} E_k {d['E_k']:.5f} eps_d {d['eps_d']:.3e} "
                       f"({time.time() - t0:.0f} s)", flush=True)
+            if partial and s > 0 and s % (every * partial) == 0:
+                write(s)
         if s < steps:
             f = lbm.step(f, prm)
-    rec = dict(source="oracle.lbm FP64, oracle.diagnostics (Eq. (7), spectral derivatives)",
-               case=dict(n=n, M0=M0, Re=Re, Pr=0.71, law={"power": "power 0.76", "sutherland": "Sutherland 0.4042", "const": "constant"}[law], f_mu=prm["f_mu"], dt=prm["dt"],
-                         C_sigma=prm["C_sigma"], J_min=prm["J_min"], omega_min=prm["omega_min"]),
-               every=every, steps=steps, wall_seconds=round(time.time() - t0, 1), history=hist)
-    with open(out, "w") as fh:
-        json.dump(rec, fh)
+    write(hist["step"][-1])
     print("wrote", out)
 
 
