@@ -270,16 +270,23 @@ def traffic_entry(storage, mean_ms):
     return rec.get("bytes_per_launch")
 
 
+# Bytes between the component runs of the ensemble's population array (the
+# component-major batch layout): 1 GiB apart, like a large lattice's regions.
+BATCH_SPACING = 1 << 30
+
+
 def run_batch(cnsf, steps, warmup, placed=True):
     """Ensemble of 64 uneven Taylor-Green lattices (FP16 storage): graph replay vs
     per-step launches vs per-member launches.  The population array is placed
     like the single lattices (Batch.placed: the fastest of several probed
-    allocations); the first candidate's probe is the plain-allocation rate."""
+    allocations), with its component runs BATCH_SPACING apart; the first
+    candidate's probe is the plain-allocation rate."""
     import torch
     import workloads as W
     cases = W.batch_ensemble(materialize=False)
     prms = [c.params for c in cases]
-    B = cnsf.Batch.placed(prms) if placed else cnsf.Batch(prms)
+    B = (cnsf.Batch.placed(prms, spacing=BATCH_SPACING) if placed
+         else cnsf.Batch(prms, spacing=BATCH_SPACING))
     for j, c in enumerate(cases):
         B.set_state(j, W.tgv_slab(c.params, 0, c.params["nz"]))
     B.autotune(os.path.join(tempfile.gettempdir(), "cnsf_batch_autotune.json"), steps_per_trial=10)
@@ -298,6 +305,8 @@ def run_batch(cnsf, steps, warmup, placed=True):
             out["graph_frac_peak"] = round(alg * steps / dt / 1e9 / PEAK_HBM_GBPS, 4)
     out["cells"] = B.ncells
     out["members"] = len(cases)
+    out["array_bytes"] = B.nbytes
+    out["component_spacing_bytes"] = BATCH_SPACING
     if placed:
         ms = B.placement_ms
         out["placement"] = dict(probe_ms=[round(x, 4) for x in ms], kept=B.placement_kept,

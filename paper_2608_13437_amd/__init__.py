@@ -506,25 +506,32 @@ class Batch:
 
     MODE_LAUNCH, MODE_GRAPH, MODE_SEQUENTIAL = 0, 1, 2
 
-    def __init__(self, prms, *, device="cuda", stream=None, buf=None):
+    def __init__(self, prms, *, device="cuda", stream=None, buf=None, spacing: int = 0):
         """buf: optional uint8 CUDA tensor of at least the required bytes for the
         members' populations (e.g. another batch's, whose state this one then
-        overwrites)."""
+        overwrites).  spacing: bytes between the runs of consecutive components
+        in the component-major layout (the library's minimum if 0); the array
+        then takes NCOMP * spacing bytes (capped by buf's size when buf is
+        given).  About 1 GiB lets MI355X run an ensemble of small members at
+        a large lattice's rate; results do not depend on it."""
         torch = _torch()
         self.prms = [dict(p) for p in prms]
         self.ps = [make_params(p) for p in prms]
-        self.nbytes = cnsf_batch_required_bytes(self.ps)
+        need = cnsf_batch_required_bytes(self.ps)
+        self.nbytes = max(need, NCOMP * int(spacing))
         if buf is not None:
-            if buf.dtype != torch.uint8 or not buf.is_cuda or buf.numel() < self.nbytes or not buf.is_contiguous():
-                raise ValueError(f"buf must be a contiguous uint8 CUDA tensor of >= {self.nbytes} bytes")
+            if buf.dtype != torch.uint8 or not buf.is_cuda or buf.numel() < need or not buf.is_contiguous():
+                raise ValueError(f"buf must be a contiguous uint8 CUDA tensor of >= {need} bytes")
             self.buf = buf
+            self.nbytes = min(self.nbytes, buf.numel())
         else:
             self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=torch.device(device))
         self.stream = stream
         self.h = cnsf_batch_create(self.ps, self.buf.data_ptr(), self.nbytes, _stream_handle(stream))
 
     @classmethod
-    def placed(cls, prms, *, candidates: int | None = None, probe_steps: int = 4, device="cuda", stream=None):
+    def placed(cls, prms, *, candidates: int | None = None, probe_steps: int = 4, device="cuda", stream=None,
+               spacing: int = 0):
         """A batch whose population array is the fastest of `candidates` allocations
         (default: as many as fit in 85% of the free device memory, at most 8),
         by the policy of Lattice.placed: each candidate batch is created
@@ -535,7 +542,7 @@ class Batch:
         candidate's mean time per step and ``placement_kept`` the index kept."""
         torch = _torch()
         torch.cuda.empty_cache()
-        need = cnsf_batch_required_bytes([make_params(p) for p in prms])
+        need = max(cnsf_batch_required_bytes([make_params(p) for p in prms]), NCOMP * int(spacing))
         if candidates is None:
             free = torch.cuda.mem_get_info(torch.device(device))[0]
             candidates = min(8, int(0.85 * free) // max(1, need))
@@ -543,7 +550,7 @@ class Batch:
         s = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
         for _ in range(max(1, int(candidates))):
             try:
-                B = cls(prms, device=device, stream=stream)
+                B = cls(prms, device=device, stream=stream, spacing=spacing)
             except torch.cuda.OutOfMemoryError:
                 if not bs:
                     raise
@@ -562,7 +569,7 @@ class Batch:
             B.close()
         del bs, B
         torch.cuda.empty_cache()
-        out = cls(prms, device=device, stream=stream, buf=buf)
+        out = cls(prms, device=device, stream=stream, buf=buf, spacing=spacing)
         out.placement_ms, out.placement_kept = ms, best
         return out
 

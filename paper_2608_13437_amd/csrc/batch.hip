@@ -114,7 +114,57 @@ struct cnsf_batch {
   uint32_t total_tiles = 0;
   int* dflag = nullptr;
   bool scaled = false;   // some member stores with a non-unit scale
+  bool interleaved = false;  // component-major population layout
 };
+
+// Population layout of a batch.  Component-major when every region fits the
+// 32-bit offsets of the buffer resources: component k of all members is one
+// run, member after member, and consecutive runs start S elements apart, so
+// a member's 14 regions lie as far apart as a large lattice's.  S is the
+// members' total slot count, or more when the caller's buffer is larger than
+// required (up to the 32-bit limit): wider spacing is what lets MI355X run an
+// ensemble at the rate of one large lattice.  Otherwise member-major: each
+// member's own population array after the previous one.
+struct BatchLayout {
+  bool interleaved = false;
+  uint64_t S = 0;                 // elements between component runs (interleaved)
+  std::vector<uint64_t> offset;   // first element of each member's component 0
+  size_t bytes = 0;               // bytes the layout occupies
+};
+
+static int batch_layout(const cnsf_params* members, int32_t n, size_t avail, BatchLayout& L) {
+  const size_t eb = elem_bytes(members[0].storage);
+  const uint64_t align = 256 / eb;              // member runs start on 256-byte boundaries
+  const uint64_t limit = ((1ull << 32) - 512) / eb / align * align;   // largest S of a 32-bit region
+  uint64_t S = 0;
+  for (int j = 0; j < n; ++j) {
+    const uint64_t nc = (uint64_t)members[j].nx * members[j].ny * members[j].nz;
+    S += (component_stride(nc, members[j].storage) + align - 1) / align * align;
+  }
+  L.offset.assign(n, 0);
+  if (S <= limit) {
+    L.interleaved = true;
+    uint64_t off = 0;
+    for (int j = 0; j < n; ++j) {
+      const uint64_t nc = (uint64_t)members[j].nx * members[j].ny * members[j].nz;
+      L.offset[j] = off;
+      off += (component_stride(nc, members[j].storage) + align - 1) / align * align;
+    }
+    const uint64_t wide = avail / ((uint64_t)NC * eb) / align * align;
+    L.S = std::max(S, std::min(wide, limit));
+    L.bytes = (size_t)NC * L.S * eb;
+    return CNSF_OK;
+  }
+  uint64_t off = 0;
+  for (int j = 0; j < n; ++j) {
+    size_t nb = 0;
+    if (int e = cnsf_required_bytes(&members[j], &nb)) return e;
+    L.offset[j] = off;
+    off += (nb + 255) / 256 * 256 / eb;
+  }
+  L.bytes = (size_t)off * eb;
+  return CNSF_OK;
+}
 
 static void batch_drop_graph(cnsf_batch* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -163,15 +213,15 @@ extern "C" {
 int cnsf_batch_required_bytes(const cnsf_params* members, int32_t n, size_t* bytes) {
   if (!members || n < 1 || !bytes) return fail(CNSF_E_INVALID, "batch needs n >= 1 members");
   if (n > 65536) return fail(CNSF_E_INVALID, "%d members: a batch holds at most 65536", n);
-  size_t tot = 0;
   for (int j = 0; j < n; ++j) {
     size_t nb = 0;
     if (int e = cnsf_required_bytes(&members[j], &nb)) return e;
     if (members[j].storage != members[0].storage) return fail(CNSF_E_INVALID, "members differ in storage");
     if (members[j].bc_x != CNSF_BC_PERIODIC) return fail(CNSF_E_INVALID, "batch members must be periodic");
-    tot += (nb + 255) / 256 * 256;
   }
-  *bytes = tot;
+  BatchLayout L;
+  if (int e = batch_layout(members, n, 0, L)) return e;
+  *bytes = L.bytes;
   return CNSF_OK;
 }
 
@@ -188,8 +238,10 @@ int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size
   b->stream = (hipStream_t)stream;
   b->bytes = need;
   (void)hipGetDevice(&b->device);
-  uint64_t off = 0;
-  const size_t eb = elem_bytes(b->storage);
+  BatchLayout lay;
+  (void)batch_layout(members, n, dev_buf ? bytes : 0, lay);   // validated by cnsf_batch_required_bytes above
+  b->bytes = lay.bytes;
+  b->interleaved = lay.interleaved;
   for (int j = 0; j < n; ++j) {
     const cnsf_params* p = &members[j];
     b->p.push_back(*p);
@@ -197,13 +249,11 @@ int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size
     b->phd.push_back(d);
     Member M{};
     M.g = derive_geom(p, d);
+    if (lay.interleaved) M.g.cstride = lay.S;   // component k of member j at offset[j] + k S
     M.ph = to_float(d);
     M.cd = derive_codec(p, d);
-    M.pop_offset = off;
+    M.pop_offset = lay.offset[j];
     if (M.cd.scaled) b->scaled = true;
-    size_t nb = 0;
-    cnsf_required_bytes(p, &nb);
-    off += (nb + 255) / 256 * 256 / eb;
     b->m.push_back(M);
   }
   hipError_t e;
@@ -231,7 +281,7 @@ int cnsf_batch_create(const cnsf_params* members, int32_t n, void* dev_buf, size
     return r;
   }
   // padding slots are never written by a step; cleared, exports are deterministic
-  e = hipMemsetAsync(b->base, 0, need, b->stream);
+  e = hipMemsetAsync(b->base, 0, b->bytes, b->stream);
   if (e != hipSuccess) {
     cnsf_batch_destroy(b);
     return hip_fail(e, "clearing the population array");

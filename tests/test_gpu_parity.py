@@ -666,10 +666,10 @@ def test_batch_matches_single_lattices():
         L.step(n)
         ref.append(L.moments())
         assert np.all(np.isfinite(ref[-1]))
-    for mode in (0, 1, 2):
+    for mode, spacing in ((0, 0), (1, 0), (2, 0), (1, 48 << 20)):
         for (block, tile, grid) in ((256, 256, 0), (128, 512, 64)):
-            log(f"batch mode {mode} block {block} tile {tile} grid {grid}")
-            B = cnsf.Batch(prms)
+            log(f"batch mode {mode} block {block} tile {tile} grid {grid} component spacing {spacing}")
+            B = cnsf.Batch(prms, spacing=spacing)
             B.set_launch(block, tile, grid, graph_steps=4)
             for j, c in enumerate(cases):
                 B.set_state(j, c.Q0)

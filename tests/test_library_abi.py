@@ -68,6 +68,24 @@ def test_params_default_and_bytes(cnsf):
     assert cnsf.cnsf_required_bytes(q) == 14 * 7 * 2048 * 4
 
 
+def test_batch_layout_bytes(cnsf):
+    """Component-major batches take 14 runs of the members' slot counts (each
+    member's run rounded to 256 bytes); batches whose runs would pass the
+    32-bit region offsets store the members one after another instead."""
+    def prm(n, storage):
+        q = W.tgv_params(n, storage=storage)
+        return cnsf.make_params(q)
+
+    slots = lambda n: 7 * -(-n ** 3 // 1024) * 1024
+    for storage, eb in ((W.STORAGE_FP32, 4), (W.STORAGE_FP16, 2)):
+        ms = [prm(n, storage) for n in (32, 48, 13)]
+        run = sum(-(-slots(n) * eb // 256) * 256 for n in (32, 48, 13))
+        assert cnsf.cnsf_batch_required_bytes(ms) == 14 * run
+    # three 512^3 FP32 members: 3 x 3.76 GB per component, past 4 GiB
+    big = [prm(512, W.STORAGE_FP32)] * 3
+    assert cnsf.cnsf_batch_required_bytes(big) == 3 * 98 * 512 ** 3 * 4
+
+
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("dt", 0.0), ("dx", -1.0), ("gamma", 1.0), ("tau_R", 0.0), ("tau_q", -1.0),
     ("omega_min", 0.0), ("omega_min", 2.5), ("tau_base_override", 0.4), ("f_mu", -1.0),
