@@ -584,11 +584,13 @@ __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict
             yv[q] = sl ? (fields + 6 * N + o)[toff] : 0.0;
             zv[q] = sl ? (fields + 7 * N + o)[toff] : 0.0;
           }
+          if (sl) {
 #pragma unroll
-          for (int q = 0; q < EB; ++q) {
-            const double d = av[q] + da.sign * S[sn * SROW + j0 + JSTEP * (q0 + q)];
-            eps_s += mv[q] * (xv[q] * xv[q] + yv[q] * yv[q] + zv[q] * zv[q]);
-            eps_d += mv[q] * d * d;
+            for (int q = 0; q < EB; ++q) {
+              const double d = av[q] + da.sign * S[sn * SROW + j0 + JSTEP * (q0 + q)];
+              eps_s += mv[q] * (xv[q] * xv[q] + yv[q] * yv[q] + zv[q] * zv[q]);
+              eps_d += mv[q] * d * d;
+            }
           }
         }
       } else {
