@@ -122,9 +122,12 @@ struct DerivAxis {
   uint32_t log2n;           // 0 if n is not a power of two
   int axis;                 // 0 x, 1 y, 2 z
   int init;                 // store into the accumulator instead of adding
-  int eps;                  // k_deriv512 only: 0 store the result; 1, 2 reduce the eps sums of the
-                            // completed fields instead (1 into the eps fields of the partials,
-                            // 2 whole partials with the other fields neutral)
+  int eps;                  // k_deriv512 only: 0 store the result; otherwise the pass completes
+                            // its field and adds mu field^2 to the block's partial instead:
+                            // 1 added to the partial's eps field, 2 the first such pass with
+                            // whole partials (other fields neutral), 3 the first such pass
+                            // into the eps fields only
+  int eps_d;                // the completed field is div u (eps_d), else a vorticity component
   double sign;
   double kscale;            // 2 pi / (n dx)
 };
@@ -464,14 +467,11 @@ __device__ inline void fft512_inv(double2 (&v)[8], double2* X, const double2* tw
 // through LDS in rows of sixteen consecutive x (whole 128-byte lines),
 // instead of 64 separate rows per load.
 //
-// The last pass (z, into div u) can also reduce the eps sums of Eq. (7): with
-// da.eps set it reads mu, omega_x, omega_y and omega_z at each point, adds
-// mu |omega|^2 and mu (div u)^2 to the block's partial, and does not store
-// div u, which nothing reads afterwards.
+// A pass that completes a field (the last of its derivative terms) can also
+// reduce its Eq. (7) sum: with da.eps set it reads mu at each point, adds
+// mu field^2 to the block's partial (eps_s for a vorticity component, eps_d
+// for div u), and does not store the field, which nothing reads afterwards.
 constexpr int W512 = 8;                            // wavefronts per block of the 512-point kernels
-#ifndef CNSF_EPS_BATCH
-#define CNSF_EPS_BATCH 2                           // points per thread whose eps inputs load together
-#endif
 template <bool EPS>
 __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict__ uc, double* __restrict__ acc,
                                                         const Geom g, const DerivAxis da,
@@ -491,7 +491,7 @@ __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict
   double2* X = xch + wave * L512_WAVE;
   const GroupRange gr = xcd_groups((da.nlines + GL - 1) / GL);
   const double kf = da.kscale / 512.0;
-  double eps_s = 0.0, eps_d = 0.0;
+  double esum = 0.0;                               // EPS: sum of mu field^2 over this thread's points
   const uint32_t kb = (lane >> 3) + 8u * (lane & 7u);   // k = kb + 64 k0 after the forward transform
   // y and z staging: thread t serves line sn = t mod GL of its group at the
   // points j0 + JSTEP q, q < PER
@@ -570,26 +570,22 @@ __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict
       }
       __syncthreads();
       if constexpr (EPS) {
-        const uint64_t N = g.ncells;
-        constexpr int EB = CNSF_EPS_BATCH;
-#pragma unroll 1
-        for (int q0 = 0; q0 < (int)PER; q0 += EB) {    // 5 EB loads in flight per batch
-          double av[EB], mv[EB], xv[EB], yv[EB], zv[EB];
+        // the completed field at each point, mu times its square summed
+        const double* mu = fields + 3 * (uint64_t)g.ncells;
 #pragma unroll
-          for (int q = 0; q < EB; ++q) {
+        for (int q0 = 0; q0 < (int)PER; q0 += 8) {
+          double av[8], mv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
             const uint64_t o = (uint64_t)(q0 + q) * qstep;
             av[q] = (sl && !da.init) ? (acc + o)[toff] : 0.0;
-            mv[q] = sl ? (fields + 3 * N + o)[toff] : 0.0;
-            xv[q] = sl ? (fields + 5 * N + o)[toff] : 0.0;
-            yv[q] = sl ? (fields + 6 * N + o)[toff] : 0.0;
-            zv[q] = sl ? (fields + 7 * N + o)[toff] : 0.0;
+            mv[q] = sl ? (mu + o)[toff] : 0.0;
           }
           if (sl) {
 #pragma unroll
-            for (int q = 0; q < EB; ++q) {
+            for (int q = 0; q < 8; ++q) {
               const double d = av[q] + da.sign * S[sn * SROW + j0 + JSTEP * (q0 + q)];
-              eps_s += mv[q] * (xv[q] * xv[q] + yv[q] * yv[q] + zv[q] * zv[q]);
-              eps_d += mv[q] * d * d;
+              esum += mv[q] * d * d;
             }
           }
         }
@@ -604,31 +600,26 @@ __global__ void __launch_bounds__(64 * W512) k_deriv512(const double* __restrict
     }
   }
   if constexpr (EPS) {
-    // block sums in a fixed order: wave shuffles, then the waves in index order
-    __shared__ double red[2][W512];
-    eps_s = wave_sum(eps_s);
-    eps_d = wave_sum(eps_d);
+    // block sum in a fixed order: wave shuffles, then the waves in index order
+    __shared__ double red[W512];
+    esum = wave_sum(esum);
     __syncthreads();
-    if (lane == 0) {
-      red[0][wave] = eps_s;
-      red[1][wave] = eps_d;
-    }
+    if (lane == 0) red[wave] = esum;
     __syncthreads();
     if (threadIdx.x == 0) {
-      double ts = red[0][0], td = red[1][0];
-      for (int w = 1; w < W512; ++w) {
-        ts += red[0][w];
-        td += red[1][w];
-      }
+      double t = red[0];
+      for (int w = 1; w < W512; ++w) t += red[w];
+      DiagPartial& P = partials[blockIdx.x];
       if (da.eps == 2) {
         DiagPartial p;
         part_zero(p);
-        p.eps_s = ts;
-        p.eps_d = td;
-        partials[blockIdx.x] = p;
+        (da.eps_d ? p.eps_d : p.eps_s) = t;
+        P = p;
+      } else if (da.eps == 3) {
+        P.eps_s = da.eps_d ? 0.0 : t;
+        P.eps_d = da.eps_d ? t : 0.0;
       } else {
-        partials[blockIdx.x].eps_s = ts;
-        partials[blockIdx.x].eps_d = td;
+        (da.eps_d ? P.eps_d : P.eps_s) += t;
       }
     }
   }
@@ -966,8 +957,12 @@ hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial
       {0, 0, 0, 1.0, 1}, {0, 1, 3, 1.0, 1}, {0, 2, 2, -1.0, 1},   // div; omega_z += d_x v; omega_y -= d_x w
       {1, 0, 3, -1.0, 0}, {1, 1, 0, 1.0, 0}, {1, 2, 1, 1.0, 1},   // omega_z -= d_y u; div; omega_x += d_y w
       {2, 0, 2, 1.0, 0}, {2, 1, 1, -1.0, 0}, {2, 2, 0, 1.0, 0}};  // omega_y += d_z u; omega_x -= d_z v; div
-  // the eps sums ride on the last pass when it takes the 512-point kernel
-  const bool fuse_eps = g.nz == 512 && CNSF_DERIV_512;
+  // With 512-point lines along y and z the eps sums ride on the passes that
+  // complete each field (omega_z in the second y pass, omega_y, omega_x and
+  // div u in the z passes), which add mu field^2 to the block partials instead
+  // of storing the field; the first of them initialises the partials' eps fields.
+  const bool fuse_eps = g.ny == 512 && g.nz == 512 && CNSF_DERIV_512;
+  int first_sum = 1;
   for (const Pass& ps : passes) {
     DerivAxis da{};
     da.n = dims[ps.a];
@@ -989,7 +984,12 @@ hipError_t launch_spectral(const Geom& g, double dx, double* fields, DiagPartial
     da.sign = ps.sign;
     da.kscale = 2.0 * M_PI / ((double)da.n * dx);
     const size_t lds = (size_t)rows * da.pairs_per_block * lds_line(da.n) * sizeof(double2) + extra;
-    if (fuse_eps && &ps == &passes[8]) da.eps = full ? 2 : 1;
+    const int k = (int)(&ps - passes);
+    if (fuse_eps && (k == 3 || k >= 6)) {
+      da.eps = first_sum ? (full ? 2 : 3) : 1;
+      da.eps_d = ps.target == 0;
+      first_sum = 0;
+    }
     if (da.n == 512 && CNSF_DERIV_512 && da.eps)
       hipLaunchKernelGGL(k_deriv512<true>, dim3(DIAG_BLOCKS), dim3(64 * W512), 0, s, fields + ps.c * N,
                          fields + (4 + ps.target) * N, g, da, (const double*)fields, partials);
