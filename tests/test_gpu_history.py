@@ -8,10 +8,10 @@ runs only the oracle:
   near local Mach 2 and the run stops at t_c = 7.5);
 * tgv64_fmu3.6_history.json: the same flow with mu ~ T^0.76 at twice that
   background dissipation, which carries it to t_c = 20;
-* tgv128_fmu0.9_M1.25_Re1600_t3_history.json: the supersonic case at 128^3
+* tgv128_fmu0.9_M1.25_Re1600_start_history.json: the supersonic case at 128^3
   with the paper's f_mu = 0.9 and mu ~ T^0.76 over the start of the run (the
-  oracle takes about 24 s per step at this size; the file holds the prefix
-  it reached, up to t_c = 3);
+  oracle takes about 27 s per step at this size; the file is the prefix of a
+  run to t_c = 3 written by make_tgv_history.py with PARTIAL set);
 * tgv32_fmu0_M0.5_Re500_history.json: the subsonic verification case of
   Section 3.2 (M0 0.5, Re 500, f_mu 0) at 32^3 to t_c = 10.
 paper_2608_13437_amd.runs repeats each case on the GPU, with the diagnostics
@@ -36,7 +36,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 CASES = [c for c in ("tgv64_fmu1.8_M1.25_Re1600_const_history.json", "tgv64_fmu3.6_history.json",
-                     "tgv128_fmu0.9_M1.25_Re1600_t3_history.json", "tgv32_fmu0_M0.5_Re500_history.json")
+                     "tgv128_fmu0.9_M1.25_Re1600_start_history.json", "tgv32_fmu0_M0.5_Re500_history.json")
          if os.path.exists(os.path.join(GOLDEN, c))]
 LAWS = {"power 0.76": "power", "Sutherland 0.4042": "sutherland", "constant": "const"}
 STORAGES = [(W.STORAGE_FP32, 0.01), (W.STORAGE_FP16, 0.02), (W.STORAGE_BF16, 0.02)]
