@@ -213,11 +213,12 @@ def cpu_baseline(n=64, steps=48, tube_steps=500):
                 shock_tubes=tubes)
 
 
-def shock_tube_timing(cnsf, steps=2000, warmup=50):
+def shock_tube_timing(cnsf, steps=2000, warmup=100):
     """Sod 256 x 4 x 4 between parity walls and Becker N x 4 x 4 (N = 128 ... 1024)
     with equilibrium ends, FP32: microseconds per step from HIP events around
-    `steps` launches on the lattice's stream.  These lattices hold 4k-16k
-    cells, so each update is one short launch: the figures are launch-bound."""
+    one call of `steps` updates on the lattice's stream.  These lattices hold
+    4k-16k cells, so each update is one short kernel; the library replays them
+    from a captured graph of 32 updates (captured during the warmup)."""
     import torch
     import workloads as W
     out = {}

@@ -71,11 +71,21 @@ _lib = None
 
 
 def library():
-    """Load libcnsf.so (in-tree build); raise if it is missing."""
+    """Load libcnsf.so (in-tree build); raise if it is missing.
+
+    torch is imported first: its wheel carries its own HIP runtime under the
+    same soname as the system one, and loading the library first would put
+    the system runtime in the process beside torch's (two runtimes, one of
+    which then finds no device).  Loaded after torch, the library binds to
+    torch's runtime, so torch's memory and streams are the library's."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2608_13437_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = C.CDLL(LIB_PATH)
         vp, i32, i64, sz, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t, C.POINTER(C.c_double)
         pp = C.POINTER(cnsf_params)

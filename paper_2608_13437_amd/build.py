@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "cnsf")
 LIB = os.path.join(PKG, "libcnsf.so")
 
-SOURCES = ["api.cpp", "update.hip", "diag.hip", "batch.hip"]
+SOURCES = ["api.cpp", "layout.cpp", "update.hip", "diag.hip", "batch.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

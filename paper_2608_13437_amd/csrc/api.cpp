@@ -39,29 +39,6 @@ const char* last_error() { return g_err.c_str(); }
 
 size_t elem_bytes(int storage) { return storage == CNSF_STORAGE_FP32 ? 4 : 2; }
 
-Launch default_launch(int storage) {
-  // Measured on the 512^3 update with the grouped slot layout: one block per
-  // tile throughout; 256-cell tiles dealt to the XCDs in contiguous spans for
-  // FP32 and BF16, 512-cell tiles in hardware order for FP16.
-  Launch lc;
-  lc.block = 256;
-  lc.tile = 256;
-  lc.grid = 0;
-  lc.remap = 1;
-  if (storage == CNSF_STORAGE_FP16) {
-    lc.tile = 512;
-    lc.remap = 0;
-  }
-  return lc;
-}
-
-// Elements between consecutive component regions: 7 slots of the cell count
-// rounded up to whole slot groups.
-uint64_t component_stride(uint64_t ncells, int storage) {
-  (void)storage;
-  return (uint64_t)NV * ((ncells + SLOT_GROUP - 1) / SLOT_GROUP * SLOT_GROUP);
-}
-
 int validate(const cnsf_params* p) {
   if (!p) return fail(CNSF_E_INVALID, "params is NULL");
   if (p->size != sizeof(cnsf_params))
@@ -258,7 +235,50 @@ struct cnsf_lattice {
   DiagPartial* step_partials = nullptr;  // per-block sums of the fused diagnostic step
   uint32_t step_partials_cap = 0;
   DiagPartial* dresult2 = nullptr;       // eps sums of the fused diagnostic step
+  // small lattices: GRAPH_STEPS updates captured once and replayed (launch-bound otherwise)
+  hipStream_t gstream = nullptr;         // capture stream
+  hipGraphExec_t gexec = nullptr;
 };
+
+namespace {
+// Lattices up to this many cells step through a replayed HIP graph when a call
+// asks for at least 2 GRAPH_STEPS updates: their update takes a few
+// microseconds, about what one launch costs.  Larger lattices launch directly.
+constexpr uint32_t GRAPH_MAX_CELLS = 1u << 21;
+constexpr int64_t GRAPH_STEPS = 32;   // even: a replay starts and ends at even parity
+
+void drop_graph(cnsf_lattice* L) {
+  if (L->gexec) (void)hipGraphExecDestroy(L->gexec);
+  L->gexec = nullptr;
+}
+
+hipError_t launch_steps(cnsf_lattice* L, int64_t n, hipStream_t s, int& parity) {
+  for (int64_t i = 0; i < n; ++i) {
+    hipError_t e = launch_update(L->p.storage, L->pop, L->g, L->ph, L->cd, parity, L->lc, s);
+    if (e != hipSuccess) return e;
+    parity ^= 1;
+  }
+  return hipSuccess;
+}
+
+// GRAPH_STEPS updates from even parity, captured on the lattice's own capture
+// stream (the caller's stream may be the null stream, which cannot capture).
+hipError_t build_graph(cnsf_lattice* L) {
+  hipError_t e = hipSuccess;
+  if (!L->gstream) e = hipStreamCreateWithFlags(&L->gstream, hipStreamNonBlocking);
+  hipGraph_t graph = nullptr;
+  if (e == hipSuccess) e = hipStreamBeginCapture(L->gstream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    int par = 0;
+    hipError_t el = launch_steps(L, GRAPH_STEPS, L->gstream, par);
+    e = hipStreamEndCapture(L->gstream, &graph);
+    if (el != hipSuccess) e = el;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&L->gexec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  return e;
+}
+}  // namespace
 
 extern "C" {
 
@@ -348,6 +368,8 @@ int cnsf_destroy(cnsf_lattice* L) {
   if (L->spec) (void)hipFree(L->spec);
   if (L->step_partials) (void)hipFree(L->step_partials);
   if (L->dresult2) (void)hipFree(L->dresult2);
+  drop_graph(L);
+  if (L->gstream) (void)hipStreamDestroy(L->gstream);
   delete L;
   return CNSF_OK;
 }
@@ -361,6 +383,7 @@ int cnsf_set_launch(cnsf_lattice* L, int32_t block, int32_t tile, int32_t grid, 
   L->lc.tile = tile;
   L->lc.grid = grid;
   L->lc.remap = xcd_remap ? 1 : 0;
+  drop_graph(L);   // the captured updates carry the old shape
   return CNSF_OK;
 }
 
@@ -410,12 +433,20 @@ int cnsf_step(cnsf_lattice* L, int64_t n) {
   if (!L) return fail(CNSF_E_INVALID, "lattice is NULL");
   if (n < 0) return fail(CNSF_E_INVALID, "n = %lld < 0", (long long)n);
   (void)hipSetDevice(L->device);
-  for (int64_t s = 0; s < n; ++s) {
-    hipError_t e = launch_update(L->p.storage, L->pop, L->g, L->ph, L->cd, L->parity, L->lc, L->stream);
-    if (e != hipSuccess) return hip_fail(e, "update launch");
-    L->parity ^= 1;
-    ++L->step;
+  int64_t left = n;
+  hipError_t e = hipSuccess;
+  if (L->g.ncells <= GRAPH_MAX_CELLS && n >= 2 * GRAPH_STEPS) {
+    if (L->parity) {
+      e = launch_steps(L, 1, L->stream, L->parity);
+      --left;
+    }
+    if (e == hipSuccess && !L->gexec) e = build_graph(L);
+    // the replays run on the caller's stream, in its order with its other work
+    for (; e == hipSuccess && left >= GRAPH_STEPS; left -= GRAPH_STEPS) e = hipGraphLaunch(L->gexec, L->stream);
   }
+  if (e == hipSuccess) e = launch_steps(L, left, L->stream, L->parity);
+  if (e != hipSuccess) return hip_fail(e, "update launch");
+  L->step += n;
   return CNSF_OK;
 }
 

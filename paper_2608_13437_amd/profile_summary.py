@@ -20,8 +20,10 @@ import re
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# the update kernel, its per-cell code, and the population layout and default
+# launch shape it runs with
 SOURCES = ["paper_2608_13437_amd/csrc/update.hip", "paper_2608_13437_amd/csrc/cnsf_impl.h",
-           "paper_2608_13437_amd/csrc/api.cpp"]   # api.cpp fixes the population layout
+           "paper_2608_13437_amd/csrc/layout.cpp"]
 
 
 def kernel_hash():

@@ -502,7 +502,7 @@ def test_set_primitive_equals_set_state(storage):
     fields: the conversion runs in FP64 on both sides, so populations can differ
     only where a last-bit FP64 difference flips their 32- or 16-bit rounding."""
     cnsf = _cnsf()
-    case = W.random_case(13, 11, 9, seed=21, sensor=True, amp=0.5)
+    case = W.sod(256, 4, 4)
     prm = dict(case.params, storage=storage)
     La, Lb = cnsf.Lattice(prm), cnsf.Lattice(prm)
     La.set_state(case.Q0)
@@ -632,6 +632,37 @@ def test_scaled_storage_keeps_small_components(storage, bound):
         assert np.array_equal(Qs, Qu)
     else:
         assert not np.array_equal(Qs, Qu) and tq_s <= tq_u
+
+
+@pytest.mark.parametrize("storage", [W.STORAGE_FP32, W.STORAGE_FP16])
+def test_graph_replayed_steps_match_single_launches(storage):
+    """Small lattices step through a captured graph of 32 updates when a call
+    asks for 64 or more: every replay, interleaved with single launches, host
+    synchronisation and a launch-shape change (which recaptures), leaves the
+    state bitwise equal to one-launch-per-step updates."""
+    cnsf = _cnsf()
+    import torch
+    case = W.sod(256, 4, 4)
+    prm = dict(case.params, storage=storage)
+    A, B = cnsf.Lattice(prm), cnsf.Lattice(prm)
+    A.set_state(case.Q0)
+    B.set_state(case.Q0)
+    for rep, n in enumerate((70, 64, 101, 3, 96)):
+        if rep == 3:
+            A.set_launch(128, 256, 0, False)
+            B.set_launch(128, 256, 0, False)
+        log(f"case sod256x4x4 storage {storage}: call {rep} of {n} steps (parity {A.info()[1]})")
+        A.step(n)
+        for _ in range(n):
+            B.step(1)
+        torch.cuda.synchronize()
+        qa, qb = A.moments(), B.moments()
+        assert np.all(np.isfinite(qa))
+        assert np.array_equal(qa, qb), (rep, float(np.max(np.abs(qa - qb))))
+        A.step(1)              # eager work between replays
+        B.step(1)
+    A.close()
+    B.close()
 
 
 def test_batch_with_scaled_members_matches_single_lattices():
