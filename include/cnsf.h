@@ -177,6 +177,9 @@ int cnsf_set_primitive(cnsf_lattice* lat, const double* P, int32_t z0, int32_t n
 
 /* Enqueue n fused stream-and-collide updates (Section 2.2, with the sensor of
  * Section 2.3; alternating even/odd in-place passes).  Asynchronous; n >= 0.
+ * Lattices of at most 2^21 cells replay a HIP graph of 32 updates, captured on
+ * first use, when n >= 64 (the results are those of single launches); while the
+ * lattice's stream is itself being captured, the updates are plain launches.
  * CNSF_E_DEVICE if a launch fails. */
 int cnsf_step(cnsf_lattice* lat, int64_t n);
 

@@ -435,7 +435,10 @@ int cnsf_step(cnsf_lattice* L, int64_t n) {
   (void)hipSetDevice(L->device);
   int64_t left = n;
   hipError_t e = hipSuccess;
-  if (L->g.ncells <= GRAPH_MAX_CELLS && n >= 2 * GRAPH_STEPS) {
+  // a caller that is capturing its own stream gets plain launches in its graph
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (L->stream) (void)hipStreamIsCapturing(L->stream, &cap);
+  if (L->g.ncells <= GRAPH_MAX_CELLS && n >= 2 * GRAPH_STEPS && cap == hipStreamCaptureStatusNone) {
     if (L->parity) {
       e = launch_steps(L, 1, L->stream, L->parity);
       --left;

@@ -665,6 +665,42 @@ def test_graph_replayed_steps_match_single_launches(storage):
     B.close()
 
 
+def test_steps_captured_by_the_caller_replay_exactly():
+    """A caller that captures its own stream around cnsf_step gets the plain
+    launches in its graph (the library's own replay is skipped while the
+    stream captures).  Each replay of the caller's graph, with eager steps and
+    host synchronisation between replays, matches one launch per step."""
+    cnsf = _cnsf()
+    import torch
+    case = W.sod(256, 4, 4)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        A = cnsf.Lattice(case.params)
+        A.set_state(case.Q0)
+    B = cnsf.Lattice(case.params)
+    B.set_state(case.Q0)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        A.step(100)                    # captured, not run: 100 updates from even parity
+    for rep in range(3):
+        log(f"case sod256x4x4: caller graph replay {rep}")
+        g.replay()
+        torch.cuda.synchronize()
+        for _ in range(100):
+            B.step(1)
+        torch.cuda.synchronize()
+        qa, qb = A.moments(), B.moments()
+        assert np.all(np.isfinite(qa))
+        assert np.array_equal(qa, qb), (rep, float(np.max(np.abs(qa - qb))))
+        with torch.cuda.stream(s):
+            A.step(2)                  # eager work; parity stays even for the next replay
+        B.step(2)
+    del g
+    A.close()
+    B.close()
+
+
 def test_batch_with_scaled_members_matches_single_lattices():
     cnsf = _cnsf()
     scale = [1.0] * 5 + [2.0 ** -8] * 9
