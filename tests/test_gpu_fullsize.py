@@ -121,13 +121,15 @@ def test_tgv512_wall_probes_match_oracle(storage, bound):
     for z0 in range(0, N, 64):
         L.set_state(W.tgv_slab(prm, z0, z0 + 64), z0=z0)
     L.step(steps)
-    got, ref = [], []
+    got, ref, qpairs, qpairs_ref = [], [], [], []
     for (zc, yc, wall), Qo in zip(gold["probes"], gold["Q"]):
         zs, ys = (np.arange(c - half, c + half) % N for c in (zc, yc))
         xs = np.arange(2 * half) if wall == 0 else np.arange(N - 2 * half, N)
         Qg = np.concatenate([L.moments(int(z), 1) for z in zs], axis=1)[:, :, ys][:, :, :, xs]
         got.append(fields(Qg, prm))
         ref.append(fields(Qo, prm))
+        qpairs.append({"Q": Qg})
+        qpairs_ref.append({"Q": Qo})
         log(f"  probe {(int(zc), int(yc), int(wall))}: rel L2 {rel_l2(got[-1], ref[-1])}")
     pooled = rel_l2({k: np.concatenate([g[k].ravel() for g in got]) for k in got[0]},
                     {k: np.concatenate([r[k].ravel() for r in ref]) for k in ref[0]})
