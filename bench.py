@@ -274,6 +274,7 @@ def traffic_entry(storage, mean_ms):
 # Bytes between the component runs of the ensemble's population array (the
 # component-major batch layout): 1 GiB apart, like a large lattice's regions.
 BATCH_SPACING = 1 << 30
+BATCH_STEPS = 2000
 
 
 def run_batch(cnsf, steps, warmup, placed=True):
@@ -306,6 +307,7 @@ def run_batch(cnsf, steps, warmup, placed=True):
             out["graph_frac_peak"] = round(alg * steps / dt / 1e9 / PEAK_HBM_GBPS, 4)
     out["cells"] = B.ncells
     out["members"] = len(cases)
+    out["steps"] = steps
     out["array_bytes"] = B.nbytes
     out["component_spacing_bytes"] = BATCH_SPACING
     if placed:
@@ -457,7 +459,8 @@ def main():
     if not args.no_tubes:
         out["shock_tubes"] = shock_tube_timing(cnsf)
     if not args.no_batch:
-        out["batch"] = run_batch(cnsf, 20, 4, placed=not args.no_placement)
+        # the ensemble configuration's 2,000 steps per member, in each mode
+        out["batch"] = run_batch(cnsf, BATCH_STEPS, 4, placed=not args.no_placement)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
