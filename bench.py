@@ -314,7 +314,7 @@ def run_batch(cnsf, steps, warmup, placed=True):
         ms = B.placement_ms
         out["placement"] = dict(probe_ms=[round(x, 4) for x in ms], kept=B.placement_kept,
                                 first_draw_MLUPS=round(B.ncells / (ms[0] * 1e-3) / 1e6, 1))
-    out["launch"] = dict(zip(("block", "tile", "grid", "graph_steps"), B.get_launch()))
+    out["launch_shape"] = dict(zip(("block", "tile", "grid", "graph_steps"), B.get_launch()))
     B.close()
     return out
 
